@@ -1,0 +1,267 @@
+"""FP64 CPU oracle of the (2+1)-D relativistic lattice Boltzmann method.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, the smoke check in
+``__graft_entry__`` and the ``cpu_baseline`` leg of ``bench.py`` may import
+this package.  The GPU library never calls it, and the two share no code:
+the oracle has its own quadrature polish (``quadrature.py``), its own
+Appendix A transcription and force matrices (``appendix.py``) and its own
+plain-C step (``rlbm_oracle.c``).
+
+Every function is pinned by a ``-m "not gpu"`` test against something the
+paper or the mathematics fixes (printed weights, exact continuum moments,
+orthonormality, closed-form Maxwell-Juttner moments, conservation laws,
+LAPACK eigenvectors, the shear viscosity).  One part is "parity unpinned":
+the higher (non-conserved) moments of the forcing term, which no closed form
+fixes; only its number, energy and momentum sources are pinned.
+"""
+from __future__ import annotations
+
+import ctypes
+import functools
+import os
+import subprocess
+
+import numpy as np
+
+from . import appendix, quadrature
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rlbm_oracle.c")
+_LIB = os.path.join(_HERE, "librlbm_oracle.so")
+
+Q = quadrature.Q
+K = 16
+
+
+def build(force: bool = True) -> str:
+    """Compile the plain-C oracle (gcc, -O2, OpenMP).  Returns the .so path."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                        "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+@functools.lru_cache(maxsize=1)
+def lib() -> ctypes.CDLL:
+    path = build(force=False)
+    L = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    L.orc_stencil_new.restype = vp
+    L.orc_stencil_new.argtypes = [_dp, _dp, _dp, _dp, _ip, _ip, _ip, _dp, _dp, _dp]
+    L.orc_stencil_free.argtypes = [vp]
+    L.orc_projections.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp]
+    L.orc_moments.argtypes = [vp, _dp, _dp, _dp]
+    L.orc_landau.argtypes = [_dp, _dp, _dp]
+    L.orc_landau.restype = ctypes.c_int
+    L.orc_macro.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_macro.restype = ctypes.c_int
+    L.orc_feq.argtypes = [vp, ctypes.c_double, ctypes.c_double, _dp, _dp]
+    L.orc_force_term.argtypes = [vp, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double,
+                                 ctypes.c_double, _dp]
+    L.orc_collide.argtypes = [vp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+    L.orc_collide.restype = ctypes.c_int
+    L.orc_lattice_new.restype = vp
+    L.orc_lattice_new.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_int, _ip, _ip, _ip, _dp, ctypes.c_void_p,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    L.orc_lattice_free.argtypes = [vp]
+    L.orc_lattice_collide.argtypes = [vp, _dp, _dp]
+    L.orc_lattice_collide.restype = ctypes.c_int
+    L.orc_lattice_stream.argtypes = [vp, _dp, _dp]
+    L.orc_lattice_run.argtypes = [vp, _dp, ctypes.c_int64]
+    L.orc_lattice_run.restype = ctypes.c_int
+    L.orc_lattice_fields.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_lattice_fields.restype = ctypes.c_int
+    L.orc_lattice_init.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
+    return L
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _iptr(a: np.ndarray):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_ip)
+
+
+class Stencil:
+    """The 48-node quadrature with its Appendix A table and force matrices."""
+
+    def __init__(self, use_printed: bool = False):
+        nodes = quadrature.node_table(use_printed)
+        self.nodes = nodes
+        self.w = np.array(nodes["w"], dtype=np.float64)
+        self.p0 = np.array(nodes["p0"], dtype=np.float64)
+        self.px = np.array(nodes["px"], dtype=np.float64)
+        self.py = np.array(nodes["py"], dtype=np.float64)
+        self.cx = np.array(nodes["cx"], dtype=np.int32)
+        self.cy = np.array(nodes["cy"], dtype=np.int32)
+        self.opp = np.array(nodes["opp"], dtype=np.int32)
+        self.J = np.ascontiguousarray(appendix.node_J_table(nodes))
+        Cx, Cy = appendix.force_matrices()
+        self.Cx = np.ascontiguousarray(Cx)
+        self.Cy = np.ascontiguousarray(Cy)
+        self._h = lib().orc_stencil_new(_ptr(self.w), _ptr(self.p0), _ptr(self.px), _ptr(self.py),
+                                        _iptr(self.cx), _iptr(self.cy), _iptr(self.opp),
+                                        _ptr(self.J), _ptr(self.Cx), _ptr(self.Cy))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_stencil_free(h)
+            self._h = None
+
+    # ---- per-site operations (each a thin call into the C oracle) ----
+    def moments(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        N = np.zeros(3)
+        T = np.zeros(9)
+        lib().orc_moments(self._h, _ptr(f), _ptr(N), _ptr(T))
+        return N, T.reshape(3, 3)
+
+    def macro(self, f):
+        """(n, T, eps, U) of one site's populations."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        out = np.zeros(3)
+        U = np.zeros(3)
+        rc = lib().orc_macro(self._h, _ptr(f), _ptr(out[0:1]), _ptr(out[1:2]), _ptr(out[2:3]), _ptr(U))
+        if rc:
+            raise ArithmeticError("no timelike Landau eigenvector")
+        return out[0], out[1], out[2], U
+
+    def feq(self, n, T, U):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        out = np.zeros(Q)
+        lib().orc_feq(self._h, float(n), float(T), _ptr(U), _ptr(out))
+        return out
+
+    def force_term(self, n, T, U, Fx, Fy):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        out = np.zeros(Q)
+        lib().orc_force_term(self._h, float(n), float(T), _ptr(U), float(Fx), float(Fy), _ptr(out))
+        return out
+
+    def collide(self, f, tau, Fx=0.0, Fy=0.0):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        out = np.zeros(Q)
+        if lib().orc_collide(self._h, _ptr(f), float(tau), float(Fx), float(Fy), _ptr(out)):
+            raise ArithmeticError("collision failed (no Landau frame)")
+        return out
+
+
+def projections(n, T, U):
+    """Appendix B projections a^(k) times n/T, App. A order."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    a = np.zeros(K)
+    lib().orc_projections(float(n), float(T), _ptr(U), _ptr(a))
+    return a
+
+
+def landau(Tm):
+    """(eps, U) of a 3x3 contravariant T^{ab}."""
+    Tm = np.ascontiguousarray(Tm, dtype=np.float64).reshape(9)
+    eps = np.zeros(1)
+    U = np.zeros(3)
+    rc = lib().orc_landau(_ptr(Tm), _ptr(eps), _ptr(U))
+    if rc:
+        raise ArithmeticError("no timelike Landau eigenvector")
+    return eps[0], U
+
+
+def four_velocity(vx, vy):
+    g = 1.0 / np.sqrt(1.0 - vx * vx - vy * vy)
+    return np.array([g, g * vx, g * vy])
+
+
+EDGES = {"bottom": 0, "top": 1, "left": 2, "right": 3}
+
+
+class Lattice:
+    """nx x ny lattice holding the pre-collision populations f (SoA, float64).
+
+    contacts: iterable of dicts {edge, start, width, n, T, vx, vy}; edge is
+    'bottom' | 'top' | 'left' | 'right' (or 0..3).  Non-periodic edges are
+    bounce-back walls except where a contact's ghost span lies.
+    """
+
+    def __init__(self, stencil: Stencil, nx: int, ny: int, *, periodic_x=False, periodic_y=False,
+                 contacts=(), solid=None, tau=1.0, F=(0.0, 0.0)):
+        self.st = stencil
+        self.nx, self.ny = int(nx), int(ny)
+        self.tau = float(tau)
+        self.F = (float(F[0]), float(F[1]))
+        contacts = list(contacts)
+        edge = np.array([EDGES.get(c["edge"], c["edge"]) if isinstance(c["edge"], str) else c["edge"]
+                         for c in contacts] or [0], dtype=np.int32)
+        start = np.array([c["start"] for c in contacts] or [0], dtype=np.int32)
+        width = np.array([c["width"] for c in contacts] or [0], dtype=np.int32)
+        state = np.array([[c.get("n", 1.0), c.get("T", 1.0), c.get("vx", 0.0), c.get("vy", 0.0)]
+                          for c in contacts] or [[0, 0, 0, 0]], dtype=np.float64).reshape(-1)
+        self._solid = None
+        sp = None
+        if solid is not None:
+            self._solid = np.ascontiguousarray(solid, dtype=np.uint8).reshape(self.ny, self.nx)
+            sp = self._solid.ctypes.data_as(ctypes.c_void_p)
+        self._h = lib().orc_lattice_new(stencil._h, self.nx, self.ny, int(periodic_x), int(periodic_y),
+                                        len(contacts), _iptr(edge), _iptr(start), _iptr(width),
+                                        _ptr(state), sp, self.tau, self.F[0], self.F[1])
+        if not self._h:
+            raise ValueError("invalid lattice description")
+        self.f = np.zeros((Q, self.ny, self.nx), dtype=np.float64)
+        self.t = 0
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_lattice_free(h)
+            self._h = None
+
+    def init_fields(self, n, T, vx, vy):
+        shape = (self.ny, self.nx)
+        arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), shape))
+                for a in (n, T, vx, vy)]
+        lib().orc_lattice_init(self._h, *[_ptr(a) for a in arrs], _ptr(self.f))
+        self.t = 0
+
+    def run(self, nsteps: int) -> None:
+        bad = lib().orc_lattice_run(self._h, _ptr(self.f), int(nsteps))
+        self.t += int(nsteps)
+        if bad:
+            raise ArithmeticError(f"{bad} site updates without a Landau frame")
+
+    def post_collision(self) -> np.ndarray:
+        out = np.empty_like(self.f)
+        if lib().orc_lattice_collide(self._h, _ptr(self.f), _ptr(out)):
+            raise ArithmeticError("collision failed")
+        return out
+
+    def fields(self):
+        """dict of n, vx, vy, eps, T arrays (ny, nx) of the current state."""
+        out = {k: np.empty((self.ny, self.nx)) for k in ("n", "vx", "vy", "eps", "T")}
+        lib().orc_lattice_fields(self._h, _ptr(self.f), _ptr(out["n"]), _ptr(out["vx"]),
+                                 _ptr(out["vy"]), _ptr(out["eps"]), _ptr(out["T"]))
+        return out
+
+    def totals(self):
+        """Lattice sums of N^0, T^00, T^0x, T^0y and N^x, N^y of the current state."""
+        f = self.f.reshape(Q, -1)
+        st = self.st
+        fs = f.sum(axis=1)
+        return {
+            "N0": float(fs @ st.p0), "Nx": float(fs @ st.px), "Ny": float(fs @ st.py),
+            "T00": float(fs @ (st.p0 * st.p0)), "T0x": float(fs @ (st.p0 * st.px)),
+            "T0y": float(fs @ (st.p0 * st.py)),
+        }
+
+
+@functools.lru_cache(maxsize=2)
+def stencil(use_printed: bool = False) -> Stencil:
+    return Stencil(use_printed)
