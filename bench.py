@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused relativistic LB step on one MI355X.
+
+Workload (default): the 1024 x 512 graphene sample -- bounce-back walls on
+every edge, source and drain contacts 32 wide on the bottom edge with
+centres 256 apart, uniform drive F = 1e-5 along +x, tau = 0.8, FP32
+populations, uniform equilibrium start -- stepped K times after W warm-up
+steps.  One step = one pass of the whole per-site update (pull with
+boundary rules, moments, Landau frame, equilibrium, force, relaxation,
+store) over every site.
+
+Prints one JSON line: MLUPS (million lattice-site updates per second), the
+HBM roofline of the step kernel (algorithmic bytes per launch over the
+average launch time measured with HIP events on the kernel's stream), and
+the FP64 CPU oracle timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+BYTES_PER_POP = {"f64": 8, "f32": 4, "f16dev": 2}
+KERNEL_SOURCES = ["paper_1804_02418_amd/csrc/step_kernels.hip", "paper_1804_02418_amd/csrc/rlbm_math.h",
+                  "paper_1804_02418_amd/csrc/rlbm_kernels.h"]
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(HERE, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name: str, sites: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(HERE, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha") != kernel_source_sha() or rec.get("sites") != sites:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def make_lattice(w, storage, stream):
+    import paper_1804_02418_amd as rl
+
+    L = rl.Lattice(w["nx"], w["ny"], storage, stream=stream)
+    L.set_boundaries(w["periodic_x"], w["periodic_y"], w["contacts"])
+    L.set_tau(w["tau"])
+    L.set_drive(*w["F"])
+    i = w["init"]
+    L.init_uniform(i["n"], i["T"], i["vx"], i["vy"])
+    return L
+
+
+def run_gpu(w, storage, steps, warmup):
+    """Returns (seconds for `steps` steps, average launch ms) timed with HIP
+    events on the lattice's stream (torch's current stream)."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    L = make_lattice(w, storage, stream.cuda_stream)
+    L.step(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    L.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    r = None
+    try:
+        r = L.residual()
+    except Exception as exc:  # health check failure is reported, not hidden
+        r = f"unstable: {exc}"
+    L.close()
+    return ms / 1e3, ms / max(steps, 1), r
+
+
+def cpu_baseline(w, steps: int):
+    import numpy as np
+
+    import oracle
+
+    st = oracle.stencil()
+    O = oracle.Lattice(st, w["nx"], w["ny"], periodic_x=w["periodic_x"], periodic_y=w["periodic_y"],
+                       contacts=w["contacts"], tau=w["tau"], F=w["F"])
+    i = w["init"]
+    O.init_fields(i["n"], i["T"], i["vx"], i["vy"])
+    t0 = time.perf_counter()
+    O.run(steps)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = min(cores, os.cpu_count() or cores)
+    return {"value": w["nx"] * w["ny"] * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{w['nx']}x{w['ny']} graphene sample, {steps} steps from the uniform start, FP64, "
+                      f"{dt:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16dev"])
+    ap.add_argument("--nx", type=int, default=1024)
+    ap.add_argument("--ny", type=int, default=512)
+    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps for the CPU baseline (0 = skip)")
+    ap.add_argument("--variants", action="store_true", help="also time the other storages and 4096x2048")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU y-slab sharding is a design "
+                                   "(DESIGN.md), not an implementation", "n_gpus": args.gpus}))
+        return 2
+
+    from paper_1804_02418_amd import workloads
+
+    w = workloads.graphene_sample(args.nx, args.ny, storage=args.storage, steps=args.steps)
+    sites = w["nx"] * w["ny"]
+    secs, launch_ms, resid = run_gpu(w, args.storage, args.steps, args.warmup)
+    mlups = sites * args.steps / secs / 1e6
+    bytes_per_launch = 2 * 48 * BYTES_PER_POP[args.storage] * sites
+    achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
+    out = {
+        "metric": "MLUPS & % HBM roofline; warm-start vs cold time-to-steady at 1e-8 residual",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(secs * 1e3 / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "f16dev": "f16 storage / f32 math"}[args.storage],
+        "data": "synthetic",
+        "config": {"workload": w["name"], "nx": w["nx"], "ny": w["ny"], "storage": args.storage, "tau": w["tau"],
+                   "drive": w["F"][0], "contacts": [[c["start"], c["width"]] for c in w["contacts"]],
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": measured_traffic(f"step_{args.storage}_{w['nx']}x{w['ny']}", sites)},
+        "residual_last_call": resid,
+    }
+    if args.variants:
+        extra = {}
+        for st in ("f64", "f16dev"):
+            s2, l2, _ = run_gpu(w, st, 2000, 100)
+            extra[f"{w['name']}_{st}"] = round(sites * 2000 / s2 / 1e6, 1)
+        big = workloads.graphene_sample(4096, 2048)
+        for st in ("f64", "f32", "f16dev"):
+            s3, l3, _ = run_gpu(big, st, 200, 20)
+            extra[f"{big['name']}_{st}"] = round(4096 * 2048 * 200 / s3 / 1e6, 1)
+        out["variants_mlups"] = extra
+    if args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

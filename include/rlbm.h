@@ -1,0 +1,201 @@
+/*
+ * rlbm.h -- C ABI of the MI355X (gfx950) library for the (2+1)-dimensional
+ * relativistic lattice Boltzmann method on a Gaussian quadrature
+ * (massless particles, third-order equilibrium, 48 populations per site).
+ *
+ * The problem the calls follow is the one of the paper's Sec. 2-3: a 2-D
+ * lattice carrying the m = 0, order-3 stencil G = {(+-3,+-4)_FS, (+-5,0)_FS}
+ * with four energy shells (Sec. 2.3), relaxed with time tau by the discrete
+ * Anderson-Witting equation (Eq. discrete-rbe), driven by an external force
+ * (Sec. 2.4), bounded by bounce-back walls and by inlet/outlet sites that do
+ * not evolve in time (Sec. 3), advanced N steps, and observed through the
+ * density n, the velocity u and the energy density eps.
+ *
+ * Conventions shared by every call:
+ *  - Lattice units: one site per unit length, one step per unit time; every
+ *    population hops ||n_i|| = 5 sites per step, so the speed of light (the
+ *    Fermi velocity of the paper's graphene application) is 5 sites/step.
+ *  - Velocities are 3-velocities u = U_s / U^0 (|u| < 1 in units of c).
+ *  - Field arrays are nx*ny float64, row-major with y the slow index:
+ *    a[y * nx + x].  on_device = 0: host pointers; 1: device pointers on the
+ *    lattice's device (e.g. torch tensor data_ptr()); the copy is ordered on
+ *    the lattice's stream.
+ *  - Population index i = 4*d + j: direction d in 0..11 sorted by angle,
+ *    (5,0),(4,3),(3,4),(0,5),(-3,4),(-4,3),(-5,0),(-4,-3),(-3,-4),(0,-5),
+ *    (3,-4),(4,-3) (opposite of d is (d+6)%12), shell j in 0..3 in the order
+ *    the paper prints the energies p0_j.
+ *  - Every call returns an rlbm_status; on failure rlbm_last_error() holds a
+ *    thread-local message.  No C++ exception crosses this boundary.
+ *  - Ownership: the library owns every device buffer it allocates (the two
+ *    population arrays, fields, constants); it never frees caller memory.
+ *    Calls on one lattice are not thread-safe; different lattices are
+ *    independent.
+ */
+#ifndef RLBM_H
+#define RLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rlbm_lattice rlbm_lattice;
+
+typedef enum {
+    RLBM_OK = 0,
+    RLBM_EINVAL = -1,    /* bad argument (sizes, tau <= 1/2, contact outside an edge, NULL handle) */
+    RLBM_ENOMEM = -2,    /* device or host allocation failed */
+    RLBM_EDEVICE = -3,   /* a HIP call failed */
+    RLBM_ESTATE = -4,    /* call out of order (e.g. step before init) */
+    RLBM_EUNSTABLE = -5  /* health check: non-finite value, n <= 0 or |u| >= 1 somewhere */
+} rlbm_status;
+
+/* Storage of the populations.  All three store the deviation
+ * (f_i - f_ref_i) / (w_i * scale) from the rest equilibrium f_ref of a
+ * reference state (n_ref, T_ref) (see rlbm_set_reference).
+ *   RLBM_F64:    float64 storage, float64 arithmetic (the parity path).
+ *   RLBM_F32:    float32 storage, float32 arithmetic; moments are turned
+ *                into the Landau frame in float64.
+ *   RLBM_F16DEV: float16 storage of the scaled deviation, float32
+ *                arithmetic, float64 Landau frame. */
+typedef enum { RLBM_F64 = 0, RLBM_F32 = 1, RLBM_F16DEV = 2 } rlbm_storage;
+
+typedef enum { RLBM_EDGE_BOTTOM = 0, RLBM_EDGE_TOP = 1, RLBM_EDGE_LEFT = 2, RLBM_EDGE_RIGHT = 3 } rlbm_edge;
+
+/* Inlet/outlet ("sites that do not evolve in time", Sec. 3): a ghost span of
+ * the five rows (columns) just outside an edge, at positions
+ * [start, start + width) along that edge (x for bottom/top, y for
+ * left/right), held at the equilibrium f^eq(n, T, u = (vx, vy)).  A
+ * population pulled from the span takes that equilibrium value; one that
+ * streams into it is absorbed. */
+typedef struct {
+    int edge;
+    int start;
+    int width;
+    double n, T, vx, vy;
+} rlbm_contact;
+
+/* ---- library-wide ---- */
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *rlbm_last_error(void);
+
+/* ABI version (incremented on incompatible changes). */
+int rlbm_version(void);
+
+/* The quadrature the library uses (Sec. 2.3): the printed weights w_1j
+ * (directions (+-3,+-4)_FS), w_2j ((+-5,0)_FS) and energies p0_j, polished on
+ * the host onto an exact solution of the orthonormality conditions
+ * (Eq. orthonormal): the solution closest to the printed values.  Host-only;
+ * needs no device.  Arrays of 4, caller-owned. */
+rlbm_status rlbm_quadrature(double w1[4], double w2[4], double p0[4]);
+
+/* The force projection matrices C_x, C_y (row-major 16x16, caller-owned),
+ * b_j = C_j a in the polynomial basis of Appendix A (Sec. 2.4), computed on
+ * the host.  Host-only. */
+rlbm_status rlbm_force_matrices(double Cx[256], double Cy[256]);
+
+/* ---- one lattice ---- */
+
+/* Create an nx x ny lattice (nx, ny >= 1) on the current HIP device.
+ * hip_stream: a hipStream_t to order all work on (NULL = the null stream).
+ * Defaults: all edges are walls, no contacts, no mask, tau = 1, no drive,
+ * reference (n_ref, T_ref) = (1, 1), scale 1 (F64/F32) or 2^-8 (F16DEV).
+ * The lattice must be initialised (rlbm_init_*) before stepping. */
+rlbm_status rlbm_create(int nx, int ny, rlbm_storage storage, void *hip_stream, rlbm_lattice **out);
+
+/* Release every device buffer of the lattice (after its stream drains).  NULL is a no-op. */
+void rlbm_destroy(rlbm_lattice *lat);
+
+/* Geometry (Sec. 3): periodic_x / periodic_y wrap that axis; every other edge
+ * is a bounce-back wall (on-site reversal, f_i(x, t+1) = f*_opp(i)(x, t))
+ * except where a contact's ghost span lies.  Precedence for a pull source
+ * outside the lattice: periodic wrap, then contact, then wall.  Contacts on a
+ * periodic edge, overlapping contacts or spans outside [0, edge length) give
+ * RLBM_EINVAL.  At most 16 contacts.  Takes effect at the next init or step. */
+rlbm_status rlbm_set_boundaries(rlbm_lattice *lat, int periodic_x, int periodic_y,
+                                const rlbm_contact *contacts, int ncontacts);
+
+/* Optional solid sites (host array nx*ny, 1 = solid, 0 = fluid; NULL clears
+ * the mask).  A pull from a solid site bounces back like a wall; solid sites
+ * are not updated and report n = u = eps = 0. */
+rlbm_status rlbm_set_mask(rlbm_lattice *lat, const uint8_t *mask);
+
+/* Relaxation (proper) time tau in steps (Eq. discrete-rbe); tau <= 1/2 gives
+ * RLBM_EINVAL.  The shear diffusivity is 6.25 (tau - 1/2) sites^2/step. */
+rlbm_status rlbm_set_tau(rlbm_lattice *lat, double tau);
+
+/* Constant external 3-force per particle F = (Fx, Fy) on every fluid site
+ * (Sec. 2.4 forcing scheme; the electrostatic drive of Sec. 3 held uniform). */
+rlbm_status rlbm_set_drive(rlbm_lattice *lat, double Fx, double Fy);
+
+/* Reference state of the deviation storage: f_ref_i = f^eq_i(n_ref, T_ref, 0)
+ * and the stored value is (f_i - f_ref_i) / (w_i * scale).  Must be called
+ * before rlbm_init_*; n_ref > 0, T_ref > 0, scale > 0. */
+rlbm_status rlbm_set_reference(rlbm_lattice *lat, double n_ref, double T_ref, double scale);
+
+/* Initial state f_i = f^eq_i(n, T, u) (Eq. feq-expansion-discrete) at every
+ * fluid site, uniform or from nx*ny fields.  Resets the step counter to 0;
+ * afterwards rlbm_read_fields returns the fields of this state. */
+rlbm_status rlbm_init_uniform(rlbm_lattice *lat, double n, double T, double vx, double vy);
+rlbm_status rlbm_init_fields(rlbm_lattice *lat, const double *n, const double *T,
+                             const double *vx, const double *vy, int on_device);
+
+/* Advance nsteps >= 0 time steps (asynchronous on the lattice's stream).  One
+ * step is, at every fluid site: pull the 48 populations along the stencil
+ * with the boundary rules, form N^a and T^ab, solve eps U^a = T^ab U_b for the
+ * Landau frame, n = U_a N^a, T = eps / (2 n), build the order-3 equilibrium and
+ * the forcing term, relax with p_i.U / (p0_i tau) and store.  The fields of the
+ * last step are kept for rlbm_read_fields. */
+rlbm_status rlbm_step(rlbm_lattice *lat, int64_t nsteps);
+
+/* Number of steps taken since the last init. */
+rlbm_status rlbm_get_time(rlbm_lattice *lat, int64_t *t);
+
+/* Fields of the current state (time t): density n, 3-velocity (vx, vy) and
+ * energy density eps.  Any pointer may be NULL.  Synchronises the stream when
+ * on_device = 0. */
+rlbm_status rlbm_read_fields(rlbm_lattice *lat, double *n, double *vx, double *vy, double *eps,
+                             int on_device);
+
+/* Residual of the last rlbm_step call of K steps, over fluid sites:
+ * r = ||u(t) - u(t-K)||_2 / (K ||u(t)||_2), in float64 (0 if ||u(t)|| = 0).
+ * Also runs the health check: RLBM_EUNSTABLE if any fluid site has a
+ * non-finite field, n <= 0 or |u| >= 1 (r is still written).  Synchronises. */
+rlbm_status rlbm_residual(rlbm_lattice *lat, double *r);
+
+/* Step until the residual over check_every steps falls below tol or
+ * max_steps have been taken; writes the steps taken and the last residual.
+ * Returns RLBM_EUNSTABLE from the health check. */
+rlbm_status rlbm_step_until(rlbm_lattice *lat, int64_t max_steps, int64_t check_every, double tol,
+                            int64_t *steps_taken, double *residual);
+
+/* Post-collision populations f*_i(x, t) of the current state as float64
+ * (48 planes of nx*ny, plane i = population i), decoded from the storage. */
+rlbm_status rlbm_read_populations(rlbm_lattice *lat, double *f, int on_device);
+
+/* Checkpoint: size of, copy out and restore the whole state (a header, the
+ * raw population storage and the fields).  rlbm_set_state requires a lattice
+ * created with the same nx, ny and storage; continuing from a restored state
+ * is bit-identical to continuing from the saved one.  Host buffers. */
+rlbm_status rlbm_state_bytes(rlbm_lattice *lat, size_t *bytes);
+rlbm_status rlbm_get_state(rlbm_lattice *lat, void *dst, size_t bytes);
+rlbm_status rlbm_set_state(rlbm_lattice *lat, const void *src, size_t bytes);
+
+/* Work decomposition of the step kernel: each block covers tile_x
+ * consecutive sites (a multiple of 64, the wavefront width) of `rows` rows,
+ * tile_x * rows <= 256.  Results do not depend on it (every site is computed
+ * independently); only speed does.  Default: tile_x = min(256, nx rounded up
+ * to 64), rows = 256 / tile_x. */
+rlbm_status rlbm_set_launch_shape(rlbm_lattice *lat, int tile_x, int rows);
+
+/* Block until all work queued on the lattice's stream is done. */
+rlbm_status rlbm_synchronize(rlbm_lattice *lat);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLBM_H */

@@ -1,0 +1,13 @@
+"""MI355X-native (gfx950) relativistic lattice Boltzmann step on a Gaussian
+quadrature (massless particles, third order, 48 populations per site).
+
+The compute path is the in-tree HIP library ``librlbm.so`` behind the C ABI
+of ``include/rlbm.h``; this package only marshals arguments to it.  Importing
+``Lattice`` or calling any function loads the library and raises if it has
+not been built: there is no CPU fallback.
+"""
+from ._binding import (EDGE, F16DEV, F32, F64, Lattice, RlbmError, Unstable, check, force_matrices, lib,
+                       quadrature)
+
+__all__ = ["Lattice", "RlbmError", "Unstable", "quadrature", "force_matrices", "lib", "check",
+           "F64", "F32", "F16DEV", "EDGE"]

@@ -1,0 +1,232 @@
+"""ctypes binding of librlbm.so (argument marshalling only; every step of the
+method runs in the library's HIP kernels).  Names follow include/rlbm.h."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librlbm.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE = 0, -1, -2, -3, -4, -5
+F64, F32, F16DEV = 0, 1, 2
+STORAGE = {"f64": F64, "f32": F32, "f16dev": F16DEV, F64: F64, F32: F32, F16DEV: F16DEV}
+EDGE = {"bottom": 0, "top": 1, "left": 2, "right": 3}
+
+
+class RlbmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"rlbm status {status}: {message}")
+        self.status = status
+
+
+class Unstable(RlbmError):
+    pass
+
+
+class rlbm_contact(ctypes.Structure):
+    _fields_ = [("edge", ctypes.c_int), ("start", ctypes.c_int), ("width", ctypes.c_int),
+                ("n", ctypes.c_double), ("T", ctypes.c_double), ("vx", ctypes.c_double), ("vy", ctypes.c_double)]
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64 = ctypes.c_int64
+
+# name -> (argtypes, restype); restype None = rlbm_status (int)
+SIGNATURES = {
+    "rlbm_last_error": ([], ctypes.c_char_p),
+    "rlbm_version": ([], ctypes.c_int),
+    "rlbm_quadrature": ([_dp, _dp, _dp], None),
+    "rlbm_force_matrices": ([_dp, _dp], None),
+    "rlbm_create": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)], None),
+    "rlbm_destroy": ([_vp], "void"),
+    "rlbm_set_boundaries": ([_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(rlbm_contact), ctypes.c_int], None),
+    "rlbm_set_mask": ([_vp, _vp], None),
+    "rlbm_set_tau": ([_vp, ctypes.c_double], None),
+    "rlbm_set_drive": ([_vp, ctypes.c_double, ctypes.c_double], None),
+    "rlbm_set_reference": ([_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double], None),
+    "rlbm_init_uniform": ([_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double], None),
+    "rlbm_init_fields": ([_vp, _vp, _vp, _vp, _vp, ctypes.c_int], None),
+    "rlbm_step": ([_vp, _i64], None),
+    "rlbm_get_time": ([_vp, ctypes.POINTER(_i64)], None),
+    "rlbm_read_fields": ([_vp, _vp, _vp, _vp, _vp, ctypes.c_int], None),
+    "rlbm_residual": ([_vp, _dp], None),
+    "rlbm_step_until": ([_vp, _i64, _i64, ctypes.c_double, ctypes.POINTER(_i64), _dp], None),
+    "rlbm_read_populations": ([_vp, _vp, ctypes.c_int], None),
+    "rlbm_state_bytes": ([_vp, ctypes.POINTER(ctypes.c_size_t)], None),
+    "rlbm_get_state": ([_vp, _vp, ctypes.c_size_t], None),
+    "rlbm_set_state": ([_vp, _vp, ctypes.c_size_t], None),
+    "rlbm_set_launch_shape": ([_vp, ctypes.c_int, ctypes.c_int], None),
+    "rlbm_synchronize": ([_vp], None),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load the in-tree librlbm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1804_02418_amd.build.build() "
+                              "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = None if res == "void" else (ctypes.c_int if res is None else res)
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> None:
+    if status != OK:
+        msg = lib().rlbm_last_error().decode(errors="replace")
+        raise (Unstable if status == EUNSTABLE else RlbmError)(status, msg)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def quadrature():
+    """(w1[4], w2[4], p0[4]) polished by the library on the host."""
+    w1, w2, p0 = np.zeros(4), np.zeros(4), np.zeros(4)
+    check(lib().rlbm_quadrature(w1.ctypes.data_as(_dp), w2.ctypes.data_as(_dp), p0.ctypes.data_as(_dp)))
+    return w1, w2, p0
+
+
+def force_matrices():
+    Cx, Cy = np.zeros(256), np.zeros(256)
+    check(lib().rlbm_force_matrices(Cx.ctypes.data_as(_dp), Cy.ctypes.data_as(_dp)))
+    return Cx.reshape(16, 16), Cy.reshape(16, 16)
+
+
+def _is_torch(a) -> bool:
+    return type(a).__module__.startswith("torch")
+
+
+class Lattice:
+    """One nx x ny lattice owned by the library (see include/rlbm.h)."""
+
+    def __init__(self, nx: int, ny: int, storage="f64", stream=None):
+        self.nx, self.ny = int(nx), int(ny)
+        self.storage = STORAGE[storage]
+        h = _vp()
+        s = _vp(stream) if stream is not None else None
+        check(lib().rlbm_create(self.nx, self.ny, self.storage, s, ctypes.byref(h)))
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().rlbm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- set-up ----
+    def set_boundaries(self, periodic_x=False, periodic_y=False, contacts=()):
+        contacts = list(contacts)
+        arr = (rlbm_contact * max(1, len(contacts)))()
+        for k, c in enumerate(contacts):
+            e = c["edge"]
+            arr[k] = rlbm_contact(EDGE.get(e, e) if isinstance(e, str) else int(e), int(c["start"]),
+                                  int(c["width"]), float(c.get("n", 1.0)), float(c.get("T", 1.0)),
+                                  float(c.get("vx", 0.0)), float(c.get("vy", 0.0)))
+        check(lib().rlbm_set_boundaries(self._h, int(bool(periodic_x)), int(bool(periodic_y)), arr, len(contacts)))
+
+    def set_mask(self, mask):
+        if mask is None:
+            check(lib().rlbm_set_mask(self._h, None))
+            return
+        m = np.ascontiguousarray(mask, dtype=np.uint8).reshape(self.ny, self.nx)
+        check(lib().rlbm_set_mask(self._h, m.ctypes.data))
+
+    def set_tau(self, tau):
+        check(lib().rlbm_set_tau(self._h, float(tau)))
+
+    def set_drive(self, Fx, Fy=0.0):
+        check(lib().rlbm_set_drive(self._h, float(Fx), float(Fy)))
+
+    def set_reference(self, n_ref=1.0, T_ref=1.0, scale=1.0):
+        check(lib().rlbm_set_reference(self._h, float(n_ref), float(T_ref), float(scale)))
+
+    def init_uniform(self, n=1.0, T=1.0, vx=0.0, vy=0.0):
+        check(lib().rlbm_init_uniform(self._h, float(n), float(T), float(vx), float(vy)))
+
+    def init_fields(self, n, T, vx, vy):
+        if all(_is_torch(a) for a in (n, T, vx, vy)):
+            ptrs = [a.contiguous().data_ptr() for a in (n, T, vx, vy)]
+            check(lib().rlbm_init_fields(self._h, *ptrs, 1))
+            return
+        shape = (self.ny, self.nx)
+        arrs = [np.ascontiguousarray(np.broadcast_to(_f64(a), shape)) for a in (n, T, vx, vy)]
+        check(lib().rlbm_init_fields(self._h, *[a.ctypes.data for a in arrs], 0))
+
+    # ---- time stepping ----
+    def step(self, nsteps: int):
+        check(lib().rlbm_step(self._h, int(nsteps)))
+
+    @property
+    def time(self) -> int:
+        t = _i64()
+        check(lib().rlbm_get_time(self._h, ctypes.byref(t)))
+        return t.value
+
+    def step_until(self, max_steps: int, check_every: int, tol: float):
+        taken, r = _i64(), ctypes.c_double()
+        check(lib().rlbm_step_until(self._h, int(max_steps), int(check_every), float(tol), ctypes.byref(taken),
+                                    ctypes.byref(r)))
+        return taken.value, r.value
+
+    # ---- observation ----
+    def read_fields(self):
+        """dict n, vx, vy, eps of numpy arrays (ny, nx)."""
+        out = {k: np.empty((self.ny, self.nx)) for k in ("n", "vx", "vy", "eps")}
+        check(lib().rlbm_read_fields(self._h, *[out[k].ctypes.data for k in ("n", "vx", "vy", "eps")], 0))
+        return out
+
+    def read_fields_device(self, n, vx, vy, eps):
+        """Copy the fields into caller-owned device buffers (torch tensors or None)."""
+        ptrs = [None if a is None else a.data_ptr() for a in (n, vx, vy, eps)]
+        check(lib().rlbm_read_fields(self._h, *ptrs, 1))
+
+    def residual(self) -> float:
+        r = ctypes.c_double()
+        check(lib().rlbm_residual(self._h, ctypes.byref(r)))
+        return r.value
+
+    def read_populations(self) -> np.ndarray:
+        f = np.empty((48, self.ny, self.nx))
+        check(lib().rlbm_read_populations(self._h, f.ctypes.data, 0))
+        return f
+
+    def get_state(self) -> bytes:
+        n = ctypes.c_size_t()
+        check(lib().rlbm_state_bytes(self._h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        check(lib().rlbm_get_state(self._h, buf, n.value))
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        check(lib().rlbm_set_state(self._h, buf, len(blob)))
+
+    def set_launch_shape(self, tile_x: int, rows: int):
+        check(lib().rlbm_set_launch_shape(self._h, int(tile_x), int(rows)))
+
+    def synchronize(self):
+        check(lib().rlbm_synchronize(self._h))

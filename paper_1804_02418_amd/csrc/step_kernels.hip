@@ -1,0 +1,402 @@
+// gfx950 kernels of the fused relativistic LB step.
+//
+// Storage: 48 SoA planes of nx*ny values, plane i = population i = 4*d + j,
+// holding the post-collision state f*(t) as the scaled deviation eta_i from
+// the reference rest equilibrium.  One step reads f*(t) from src and writes
+// f*(t+1) to dst (ping-pong), so every stored value is read exactly once
+// and written exactly once per step: the step is bound by HBM bandwidth.
+//
+// Work mapping: one thread per site; a block covers tile_x consecutive
+// sites of `rows` rows, so each wavefront reads 64 consecutive values of a
+// plane row (shifted by the hop) and writes 64 aligned values.  Blocks whose
+// 5-site halo lies inside the lattice (and without a solid mask) take a
+// branch-free gather; the others resolve periodic wrap, contact ghost spans
+// and bounce-back per population.
+#include "rlbm_kernels.h"
+
+namespace rlbm {
+namespace {
+
+template <class S>
+struct StoreIO;
+template <>
+struct StoreIO<double> {
+    template <class R>
+    __device__ static R load(const double *p) { return R(*p); }
+    template <class R>
+    __device__ static void store(double *p, R v) { *p = double(v); }
+};
+template <>
+struct StoreIO<float> {
+    template <class R>
+    __device__ static R load(const float *p) { return R(*p); }
+    template <class R>
+    __device__ static void store(float *p, R v) { *p = float(v); }
+};
+template <>
+struct StoreIO<_Float16> {
+    template <class R>
+    __device__ static R load(const _Float16 *p) { return R(float(*p)); }
+    template <class R>
+    __device__ static void store(_Float16 *p, R v) { *p = _Float16(float(v)); }
+};
+
+struct SiteFields {
+    double n, vx, vy, eps;
+};
+
+// Collision of one site, in place on the 48 scaled deviations h.
+// Steps: moments -> Landau frame -> n, T -> Appendix B projections ->
+// equilibrium and forcing polynomials -> relaxation with
+// omega_d = p_i.U / (p0_i tau) = (U^0 - nhat_d . U_s) / tau.
+template <class R>
+__device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, SiteFields &out)
+{
+    // ---- moments of the deviation, one pair of opposite directions at a time ----
+    R N0 = 0, Nx = 0, Ny = 0, T00 = 0, T0x = 0, T0y = 0, Txx = 0, Txy = 0, Tyy = 0;
+#pragma unroll
+    for (int d = 0; d < kDirs / 2; ++d) {
+        const int g = kGroup[d];
+        R a1 = 0, a2 = 0, b1 = 0, b2 = 0;
+#pragma unroll
+        for (int j = 0; j < kShells; ++j) {
+            a1 += A.wp0[g][j] * h[4 * d + j];
+            a2 += A.wp0[g][j] * h[4 * (d + 6) + j];
+            b1 += A.wp0sq[g][j] * h[4 * d + j];
+            b2 += A.wp0sq[g][j] * h[4 * (d + 6) + j];
+        }
+        const DirTrig tg = dir_trig(d);
+        const R c = R(tg.c), s = R(tg.s);
+        const R Ae = a1 + a2, Ao = a1 - a2, Be = b1 + b2, Bo = b1 - b2;
+        N0 += Ae;
+        Nx += Ao * c;
+        Ny += Ao * s;
+        T00 += Be;
+        T0x += Bo * c;
+        T0y += Bo * s;
+        Txx += Be * (c * c);
+        Txy += Be * (c * s);
+        Tyy += Be * (s * s);
+    }
+    // ---- Landau frame in float64, reference moments added back ----
+    const double nT = A.n_ref * A.T_ref;
+    const double dN0 = A.n_ref + double(N0), dNx = double(Nx), dNy = double(Ny);
+    double eps, u0, ux, uy;
+    const bool ok = landau_frame(2.0 * nT + double(T00), double(T0x), double(T0y), nT + double(Txx), double(Txy),
+                                 nT + double(Tyy), eps, u0, ux, uy);
+    const double n = u0 * dN0 - ux * dNx - uy * dNy;
+    const double T = eps / (2.0 * n);
+    out.n = n;
+    out.vx = ux / u0;
+    out.vy = uy / u0;
+    out.eps = eps;
+    // ---- equilibrium and force coefficients (deviation from the reference, / scale) ----
+    double a[kK];
+    appendix_b(n, T, u0, ux, uy, a);
+    R ad[kK];
+#pragma unroll
+    for (int k = 0; k < kK; ++k) ad[k] = R((a[k] - A.a_ref[k]) * A.inv_scale);
+    R Ha[kK], Hb[kK];
+    appendix_a_to_harmonics(ad, Ha);
+    if (A.has_force) {
+        R b[kK];
+#pragma unroll
+        for (int k = 0; k < kK; ++k) b[k] = A.cf_aref[k];
+#pragma unroll
+        for (int q = 0; q < kForceNnz; ++q) b[kForceK[q]] += A.cf[q] * ad[kForceM[q]];
+        appendix_a_to_harmonics(b, Hb);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kK; ++k) Hb[k] = R(0);
+    }
+    // ---- relaxation plus forcing, one pair of opposite directions at a time ----
+    const R U0 = R(u0 * A.tau_inv), Ux = R(ux * A.tau_inv), Uy = R(uy * A.tau_inv);
+#pragma unroll
+    for (int d = 0; d < kDirs / 2; ++d) {
+        const DirTrig tg = dir_trig(d);
+        R Ea[4], Oa[4], Eb[4], Ob[4];
+        harmonics_pair(Ha, tg, Ea, Oa);
+        harmonics_pair(Hb, tg, Eb, Ob);
+        const R proj = Ux * R(tg.c) + Uy * R(tg.s);
+        const R wp = U0 - proj, wm = U0 + proj;  // omega of d and of d + 6
+        R Gp[4], Gm[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            Gp[e] = wp * (Ea[e] + Oa[e]) - (Eb[e] + Ob[e]);
+            Gm[e] = wm * (Ea[e] - Oa[e]) - (Eb[e] - Ob[e]);
+        }
+#pragma unroll
+        for (int j = 0; j < kShells; ++j) {
+            const R p = A.p0[j];
+            const R qp = ((Gp[3] * p + Gp[2]) * p + Gp[1]) * p + Gp[0];
+            const R qm = ((Gm[3] * p + Gm[2]) * p + Gm[1]) * p + Gm[0];
+            h[4 * d + j] = (R(1) - wp) * h[4 * d + j] + qp;
+            h[4 * (d + 6) + j] = (R(1) - wm) * h[4 * (d + 6) + j] + qm;
+        }
+    }
+    return ok;
+}
+
+template <class R>
+__device__ __forceinline__ void write_fields(const StepArgs<R> &A, long long site, const SiteFields &f, bool ok)
+{
+    if (!ok) {
+        A.fn[site] = NAN;
+        A.fvx[site] = NAN;
+        A.fvy[site] = NAN;
+        A.feps[site] = NAN;
+        return;
+    }
+    A.fn[site] = f.n;
+    A.fvx[site] = f.vx;
+    A.fvy[site] = f.vy;
+    A.feps[site] = f.eps;
+}
+
+template <class S, class R>
+__global__ __launch_bounds__(256) void step_kernel(const StepArgs<R> A, const S *__restrict__ src,
+                                                   S *__restrict__ dst)
+{
+    const int tile_x = blockDim.x;
+    const int x = blockIdx.x * tile_x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int nx = A.nx, ny = A.ny;
+    const long long P = A.plane;
+    const int x0 = blockIdx.x * tile_x, y0 = blockIdx.y * blockDim.y;
+    const bool interior = !A.has_mask && x0 >= kReach && x0 + tile_x + kReach <= nx && y0 >= kReach &&
+                          y0 + (int)blockDim.y + kReach <= ny;
+    if (x >= nx || y >= ny) return;
+    const long long site = (long long)y * nx + x;
+    R h[kQ];
+    if (interior) {
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const int d = i / kShells;
+            const long long off = (long long)i * P + site - ((long long)kCy[d] * nx + kCx[d]);
+            h[i] = StoreIO<S>::template load<R>(src + off);
+        }
+    } else {
+        if (A.has_mask && A.mask[site]) {
+            if (A.write_fields) {
+                A.fn[site] = 0.0;
+                A.fvx[site] = 0.0;
+                A.fvy[site] = 0.0;
+                A.feps[site] = 0.0;
+            }
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const int d = i / kShells;
+            const int o = 4 * ((d + kDirs / 2) % kDirs) + (i % kShells);
+            int sx = x - kCx[d], sy = y - kCy[d];
+            if (A.periodic_x && (sx < 0 || sx >= nx)) sx = ((sx % nx) + nx) % nx;
+            if (A.periodic_y && (sy < 0 || sy >= ny)) sy = ((sy % ny) + ny) % ny;
+            const bool inside = sx >= 0 && sx < nx && sy >= 0 && sy < ny;
+            R v;
+            if (inside) {
+                const long long s2 = (long long)sy * nx + sx;
+                if (A.has_mask && A.mask[s2])
+                    v = StoreIO<S>::template load<R>(src + (long long)o * P + site);
+                else
+                    v = StoreIO<S>::template load<R>(src + (long long)i * P + s2);
+            } else {
+                int c = -1;
+                if (sy < 0 && sx >= 0 && sx < nx)
+                    c = A.edge_contact[sx];
+                else if (sy >= ny && sx >= 0 && sx < nx)
+                    c = A.edge_contact[nx + sx];
+                else if (sx < 0 && sy >= 0 && sy < ny)
+                    c = A.edge_contact[2 * nx + sy];
+                else if (sx >= nx && sy >= 0 && sy < ny)
+                    c = A.edge_contact[2 * nx + ny + sy];
+                if (c >= 0)
+                    v = A.contact_eta[c * kQ + i];
+                else
+                    v = StoreIO<S>::template load<R>(src + (long long)o * P + site);
+            }
+            h[i] = v;
+        }
+    }
+    SiteFields f;
+    const bool ok = collide_site<R>(h, A, f);
+    if (A.write_fields) write_fields(A, site, f, ok);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) StoreIO<S>::template store<R>(dst + (long long)i * P + site, h[i]);
+}
+
+template <class S, class R>
+__global__ __launch_bounds__(256) void init_kernel(const StepArgs<R> A, const double *__restrict__ n_in,
+                                                   const double *__restrict__ T_in, const double *__restrict__ vx_in,
+                                                   const double *__restrict__ vy_in, double un, double uT, double uvx,
+                                                   double uvy, S *__restrict__ dst)
+{
+    const long long site = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= A.plane) return;
+    if (A.has_mask && A.mask[site]) {
+        for (int i = 0; i < kQ; ++i) StoreIO<S>::template store<R>(dst + (long long)i * A.plane + site, R(0));
+        A.fn[site] = 0.0;
+        A.fvx[site] = 0.0;
+        A.fvy[site] = 0.0;
+        A.feps[site] = 0.0;
+        return;
+    }
+    const double n = n_in ? n_in[site] : un;
+    const double T = T_in ? T_in[site] : uT;
+    const double vx = vx_in ? vx_in[site] : uvx;
+    const double vy = vy_in ? vy_in[site] : uvy;
+    const double g = 1.0 / sqrt(1.0 - vx * vx - vy * vy);
+    double a[kK];
+    appendix_b(n, T, g, g * vx, g * vy, a);
+    R ad[kK], H[kK];
+    for (int k = 0; k < kK; ++k) ad[k] = R((a[k] - A.a_ref[k]) * A.inv_scale);
+    appendix_a_to_harmonics(ad, H);
+    R h[kQ];
+#pragma unroll
+    for (int d = 0; d < kDirs / 2; ++d) {
+        R E[4], O[4];
+        harmonics_pair(H, dir_trig(d), E, O);
+#pragma unroll
+        for (int j = 0; j < kShells; ++j) {
+            const R p = A.p0[j];
+            h[4 * d + j] = (((E[3] + O[3]) * p + (E[2] + O[2])) * p + (E[1] + O[1])) * p + (E[0] + O[0]);
+            h[4 * (d + 6) + j] = (((E[3] - O[3]) * p + (E[2] - O[2])) * p + (E[1] - O[1])) * p + (E[0] - O[0]);
+        }
+    }
+    SiteFields f;
+    const bool ok = collide_site<R>(h, A, f);
+    write_fields(A, site, f, ok);
+    for (int i = 0; i < kQ; ++i) StoreIO<S>::template store<R>(dst + (long long)i * A.plane + site, h[i]);
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void decode_kernel(long long plane, const S *__restrict__ src,
+                                                     const double *__restrict__ fref,
+                                                     const double *__restrict__ wscale, double *__restrict__ f)
+{
+    const long long site = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= plane) return;
+    for (int i = 0; i < kQ; ++i) {
+        const double e = StoreIO<S>::template load<double>(src + (long long)i * plane + site);
+        f[(long long)i * plane + site] = fref[i] + wscale[i] * e;
+    }
+}
+
+__global__ __launch_bounds__(256) void residual_kernel(int nsites, const unsigned char *__restrict__ mask,
+                                                       const double *__restrict__ n, const double *__restrict__ vx,
+                                                       const double *__restrict__ vy, const double *__restrict__ pvx,
+                                                       const double *__restrict__ pvy, double *__restrict__ part)
+{
+    double dv = 0.0, vv = 0.0, bad = 0.0;
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < nsites; s += gridDim.x * blockDim.x) {
+        if (mask && mask[s]) continue;
+        const double a = vx[s], b = vy[s], dn = n[s];
+        const double ex = a - pvx[s], ey = b - pvy[s];
+        const double v2 = a * a + b * b;
+        if (!(dn > 0.0) || !(v2 < 1.0) || !isfinite(a) || !isfinite(b) || !isfinite(dn)) bad += 1.0;
+        dv += ex * ex + ey * ey;
+        vv += v2;
+    }
+    // wavefront reduction (64 lanes), then across the block's wavefronts
+    for (int off = 32; off > 0; off >>= 1) {
+        dv += __shfl_down(dv, off, 64);
+        vv += __shfl_down(vv, off, 64);
+        bad += __shfl_down(bad, off, 64);
+    }
+    __shared__ double red[3][256 / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wid] = dv;
+        red[1][wid] = vv;
+        red[2][wid] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0, s1 = 0, s2 = 0;
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) {
+            s0 += red[0][w];
+            s1 += red[1][w];
+            s2 += red[2][w];
+        }
+        part[3 * blockIdx.x + 0] = s0;
+        part[3 * blockIdx.x + 1] = s1;
+        part[3 * blockIdx.x + 2] = s2;
+    }
+}
+
+template <class S, class R>
+hipError_t launch_step_t(const void *args, const void *src, void *dst, LaunchShape sh, hipStream_t s)
+{
+    const StepArgs<R> &A = *static_cast<const StepArgs<R> *>(args);
+    dim3 block(sh.tile_x, sh.rows);
+    dim3 grid((A.nx + sh.tile_x - 1) / sh.tile_x, (A.ny + sh.rows - 1) / sh.rows);
+    hipLaunchKernelGGL((step_kernel<S, R>), grid, block, 0, s, A, static_cast<const S *>(src), static_cast<S *>(dst));
+    return hipGetLastError();
+}
+
+template <class S, class R>
+hipError_t launch_init_t(const void *args, const double *n, const double *T, const double *vx, const double *vy,
+                         const double u[4], void *dst, hipStream_t s)
+{
+    const StepArgs<R> &A = *static_cast<const StepArgs<R> *>(args);
+    const int block = 256;
+    const long long grid = (A.plane + block - 1) / block;
+    hipLaunchKernelGGL((init_kernel<S, R>), dim3((unsigned)grid), dim3(block), 0, s, A, n, T, vx, vy, u[0], u[1], u[2],
+                       u[3], static_cast<S *>(dst));
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_step(Store st, const void *args, const void *src, void *dst, LaunchShape shape, hipStream_t s)
+{
+    if (shape.tile_x <= 0 || shape.rows <= 0 || shape.tile_x * shape.rows > 256 || shape.tile_x % 64)
+        return hipErrorInvalidValue;
+    switch (st) {
+    case Store::F64: return launch_step_t<double, double>(args, src, dst, shape, s);
+    case Store::F32: return launch_step_t<float, float>(args, src, dst, shape, s);
+    case Store::F16: return launch_step_t<_Float16, float>(args, src, dst, shape, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_init(Store st, const void *args, const double *n, const double *T, const double *vx,
+                       const double *vy, const double u[4], void *dst, hipStream_t s)
+{
+    switch (st) {
+    case Store::F64: return launch_init_t<double, double>(args, n, T, vx, vy, u, dst, s);
+    case Store::F32: return launch_init_t<float, float>(args, n, T, vx, vy, u, dst, s);
+    case Store::F16: return launch_init_t<_Float16, float>(args, n, T, vx, vy, u, dst, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_decode(Store st, int nx, int ny, const void *src, const double *fref, const double *wscale,
+                         double *f, hipStream_t s)
+{
+    const long long plane = (long long)nx * ny;
+    const int block = 256;
+    const dim3 grid((unsigned)((plane + block - 1) / block));
+    switch (st) {
+    case Store::F64:
+        hipLaunchKernelGGL(decode_kernel<double>, grid, dim3(block), 0, s, plane, (const double *)src, fref, wscale, f);
+        break;
+    case Store::F32:
+        hipLaunchKernelGGL(decode_kernel<float>, grid, dim3(block), 0, s, plane, (const float *)src, fref, wscale, f);
+        break;
+    case Store::F16:
+        hipLaunchKernelGGL(decode_kernel<_Float16>, grid, dim3(block), 0, s, plane, (const _Float16 *)src, fref,
+                           wscale, f);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(int nsites, const unsigned char *mask, const double *n, const double *vx, const double *vy,
+                           const double *pvx, const double *pvy, double *part, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(residual_kernel, dim3(nblocks), dim3(256), 0, s, nsites, mask, n, vx, vy, pvx, pvy, part);
+    return hipGetLastError();
+}
+
+}  // namespace rlbm

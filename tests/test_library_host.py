@@ -1,0 +1,79 @@
+"""CPU checks of the GPU library: it loads, exports every symbol of
+include/rlbm.h, and its host-side constants (quadrature polish and force
+matrices, computed independently of the oracle) agree with the oracle's.
+No call here touches a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(rlbm_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1804_02418_amd as rl
+
+    L = rl.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 20
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    # the binding covers the same set
+    from paper_1804_02418_amd import _binding
+
+    assert declared <= set(_binding.SIGNATURES), declared - set(_binding.SIGNATURES)
+
+
+def test_library_quadrature_matches_oracle():
+    import paper_1804_02418_amd as rl
+    from oracle import quadrature
+
+    w1, w2, p0 = rl.quadrature()
+    o1, o2, op = quadrature.shell_tables()
+    # both polishes solve for 12 unknowns of order 1e-4..8 jointly; agreement
+    # is to ~1e-19 in absolute terms (the tiny shell p0_1 ~ 1.6e-5 included)
+    np.testing.assert_allclose(w1, o1, rtol=4e-16, atol=1e-18)
+    np.testing.assert_allclose(w2, o2, rtol=4e-16, atol=1e-18)
+    np.testing.assert_allclose(p0, op, rtol=4e-16, atol=1e-18)
+
+
+def test_library_force_matrices_match_oracle():
+    import paper_1804_02418_amd as rl
+    from oracle import appendix
+
+    Cx, Cy = rl.force_matrices()
+    ox, oy = appendix.force_matrices()
+    assert np.abs(Cx - ox).max() < 1e-15
+    assert np.abs(Cy - oy).max() < 1e-15
+
+
+@pytest.mark.parametrize("nx,ny,storage", [(0, 8, 0), (8, -1, 1), (8, 8, 7)])
+def test_create_rejects_invalid_arguments(nx, ny, storage):
+    import paper_1804_02418_amd as rl
+    from paper_1804_02418_amd import _binding
+
+    h = ctypes.c_void_p()
+    st = rl.lib().rlbm_create(nx, ny, storage, None, ctypes.byref(h))
+    assert st == _binding.EINVAL
+    assert rl.lib().rlbm_last_error()
+
+
+def test_null_handle_is_rejected():
+    import paper_1804_02418_amd as rl
+    from paper_1804_02418_amd import _binding
+
+    assert rl.lib().rlbm_set_tau(None, 1.0) == _binding.EINVAL
+    assert rl.lib().rlbm_step(None, 1) == _binding.EINVAL
+    rl.lib().rlbm_destroy(None)
