@@ -110,6 +110,28 @@ def cpu_baseline(w, steps: int):
                       f"{dt:.1f} s"}
 
 
+def copy_calibration(nbytes: int, reps: int = 20):
+    """Plain device-to-device copy of nbytes (torch), timed with HIP events:
+    the practical HBM bandwidth, and the kernel whose FETCH_SIZE / WRITE_SIZE
+    counters calibrate the step kernel's measured traffic."""
+    import torch
+
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"copy_bytes": nbytes, "read_plus_write_GBs": round(2 * nbytes / (ms / 1e3) / 1e9, 1),
+            "ms_per_copy": round(ms, 4)}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,7 +142,12 @@ def main(argv=None):
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps for the CPU baseline (0 = skip)")
     ap.add_argument("--variants", action="store_true", help="also time the other storages and 4096x2048")
+    ap.add_argument("--copy-bytes", type=int, default=0, help="only run the copy-bandwidth calibration")
     args = ap.parse_args(argv)
+
+    if args.copy_bytes:
+        print(json.dumps(copy_calibration(args.copy_bytes)), flush=True)
+        return 0
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU y-slab sharding is a design "

@@ -102,7 +102,7 @@ rlbm_status rlbm_force_matrices(double Cx[256], double Cy[256]);
 /* Create an nx x ny lattice (nx, ny >= 1) on the current HIP device.
  * hip_stream: a hipStream_t to order all work on (NULL = the null stream).
  * Defaults: all edges are walls, no contacts, no mask, tau = 1, no drive,
- * reference (n_ref, T_ref) = (1, 1), scale 1 (F64/F32) or 2^-8 (F16DEV).
+ * reference (n_ref, T_ref) = (1, 1), scale 1 (F64/F32) or 2^-12 (F16DEV).
  * The lattice must be initialised (rlbm_init_*) before stepping. */
 rlbm_status rlbm_create(int nx, int ny, rlbm_storage storage, void *hip_stream, rlbm_lattice **out);
 
@@ -184,11 +184,12 @@ rlbm_status rlbm_state_bytes(rlbm_lattice *lat, size_t *bytes);
 rlbm_status rlbm_get_state(rlbm_lattice *lat, void *dst, size_t bytes);
 rlbm_status rlbm_set_state(rlbm_lattice *lat, const void *src, size_t bytes);
 
-/* Work decomposition of the step kernel: each block covers tile_x
- * consecutive sites (a multiple of 64, the wavefront width) of `rows` rows,
- * tile_x * rows <= 256.  Results do not depend on it (every site is computed
- * independently); only speed does.  Default: tile_x = min(256, nx rounded up
- * to 64), rows = 256 / tile_x. */
+/* Work decomposition of the step kernel: each 256-thread block of the
+ * lattice interior covers tile_x consecutive sites (64, 128 or 256: a
+ * multiple of the 64-wide wavefront) of rows = 256 / tile_x rows.  Results do
+ * not depend on it (every site is computed independently); only speed does.
+ * Default: the largest of 64/128/256 not above the interior width rounded up
+ * to 64. */
 rlbm_status rlbm_set_launch_shape(rlbm_lattice *lat, int tile_x, int rows);
 
 /* Block until all work queued on the lattice's stream is done. */

@@ -109,17 +109,32 @@ void orc_projections(double n, double T, const double U[3], double a[K])
 
 /* --------------------------------------------------------------- moments */
 
+/* Compensated (Neumaier) accumulation: the sum is the same sum, evaluated to
+ * about one rounding of the result instead of a rounding of every partial
+ * sum, so that the oracle's own round-off does not grow with the size of the
+ * populations when the moment itself (e.g. T^0x of a slow flow) is small. */
+typedef struct { double s, c; } orc_acc;
+
+static void acc_add(orc_acc *a, double v)
+{
+    const double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+
 void orc_moments(const orc_stencil *s, const double *f, double N[3], double Tm[9])
 {
-    for (int a = 0; a < 3; ++a) N[a] = 0.0;
-    for (int a = 0; a < 9; ++a) Tm[a] = 0.0;
+    orc_acc n[3] = {{0, 0}}, t[9] = {{0, 0}};
     for (int i = 0; i < Q; ++i) {
         const double p[3] = {s->p0[i], s->px[i], s->py[i]};
         for (int a = 0; a < 3; ++a) {
-            N[a] += f[i] * p[a];
-            for (int b = 0; b < 3; ++b) Tm[3 * a + b] += f[i] * p[a] * p[b];
+            acc_add(&n[a], f[i] * p[a]);
+            for (int b = 0; b < 3; ++b) acc_add(&t[3 * a + b], f[i] * p[a] * p[b]);
         }
     }
+    for (int a = 0; a < 3; ++a) N[a] = n[a].s + n[a].c;
+    for (int a = 0; a < 9; ++a) Tm[a] = t[a].s + t[a].c;
 }
 
 /* Landau frame: the timelike eigenvector of M^a_b = T^ac eta_cb,

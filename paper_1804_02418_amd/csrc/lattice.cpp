@@ -46,13 +46,22 @@ rlbm_status load_constants(Consts *c)
 {
     const char *err = nullptr;
     if (!host_constants(&c->q, c->Cx, c->Cy, &err)) return fail(RLBM_EDEVICE, "constants: %s", err ? err : "?");
-    // the kernels skip the entries outside the compile-time force pattern
-    bool in_pattern[kK][kK] = {};
-    for (int q = 0; q < kForceNnz; ++q) in_pattern[kForceK[q]][kForceM[q]] = true;
+    // the kernels carry the non-zero entries of C_x, C_y as constants: they
+    // must equal this exact computation, and every other entry must vanish
+    double tx[kK][kK] = {}, ty[kK][kK] = {};
+    for (int q = 0; q < kForceNx; ++q) tx[kForceX[q].k][kForceX[q].m] = kForceX[q].v;
+    for (int q = 0; q < kForceNy; ++q) ty[kForceY[q].k][kForceY[q].m] = kForceY[q].v;
     for (int k = 0; k < kK; ++k)
         for (int m = 0; m < kK; ++m)
-            if (!in_pattern[k][m] && (std::fabs(c->Cx[k][m]) > 1e-15 || std::fabs(c->Cy[k][m]) > 1e-15))
-                return fail(RLBM_EDEVICE, "force matrix entry (%d,%d) outside the kernel pattern", k, m);
+            if (std::fabs(c->Cx[k][m] - tx[k][m]) > 1e-15 || std::fabs(c->Cy[k][m] - ty[k][m]) > 1e-15)
+                return fail(RLBM_EDEVICE, "force matrix entry (%d,%d) differs from the kernel constant", k, m);
+    // the reference rest frame has projections only at kRestK
+    double a[kK];
+    appendix_b(1.3, 0.7, 1.0, 0.0, 0.0, a);
+    for (int k = 0; k < kK; ++k) {
+        const bool rest = k == kRestK[0] || k == kRestK[1] || k == kRestK[2] || k == kRestK[3];
+        if (!rest && a[k] != 0.0) return fail(RLBM_EDEVICE, "rest-frame projection %d is not zero", k);
+    }
     return RLBM_OK;
 }
 
@@ -103,6 +112,8 @@ struct rlbm_lattice {
     double *part = nullptr;
     int part_blocks = 0;
     double *fref = nullptr, *wscale = nullptr;
+    unsigned *gtab = nullptr;  // boundary gather table
+    long long gtab_rows = 0;
     // argument blocks (one is used, by storage)
     StepArgs<double> args_d{};
     StepArgs<float> args_f{};
@@ -138,17 +149,13 @@ void fill_args(rlbm_lattice *L, StepArgs<R> &A)
     appendix_b(L->n_ref, L->T_ref, 1.0, 0.0, 0.0, A.a_ref);
     A.inv_scale = 1.0 / L->scale;
     A.tau_inv = 1.0 / L->tau;
-    double CF[kK][kK];
-    for (int k = 0; k < kK; ++k)
-        for (int m = 0; m < kK; ++m) CF[k][m] = L->Fx * L->C.Cx[k][m] + L->Fy * L->C.Cy[k][m];
-    for (int qn = 0; qn < kForceNnz; ++qn) A.cf[qn] = R(CF[kForceK[qn]][kForceM[qn]]);
-    for (int k = 0; k < kK; ++k) {
-        double s = 0;
-        for (int m = 0; m < kK; ++m) s += CF[k][m] * A.a_ref[m];
-        A.cf_aref[k] = R(s / L->scale);
-    }
+    A.fx = R(L->Fx);
+    A.fy = R(L->Fy);
+    for (int r = 0; r < 4; ++r) A.aref_s[r] = R(A.a_ref[kRestK[r]] / L->scale);
     A.mask = L->mask;
     A.edge_contact = L->edge;
+    A.gather_tab = L->gtab;
+    A.nbnd = L->gtab_rows;
     A.contact_eta = static_cast<const R *>(L->contact_eta);
     A.fn = L->fld;
     A.fvx = L->fld + L->plane();
@@ -156,8 +163,58 @@ void fill_args(rlbm_lattice *L, StepArgs<R> &A)
     A.feps = L->fld + 3 * L->plane();
 }
 
-// Upload boundary tables and rebuild the kernel argument blocks.
-rlbm_status refresh(rlbm_lattice *L)
+// Boundary rules of the pull (periodic wrap, then contact span, then
+// bounce-back, a solid source also bouncing back) resolved on the host for
+// every boundary site: the source element of each population, or a contact
+// equilibrium.  Used while 48 * nx * ny fits in 31 bits.
+rlbm_status build_gather_table(rlbm_lattice *L, const std::vector<signed char> &edge)
+{
+    hipFree(L->gtab);
+    L->gtab = nullptr;
+    L->gtab_rows = 0;
+    const long long P = L->plane();
+    if (P * kQ >= (1LL << 31)) return RLBM_OK;  // computed gather for huge lattices
+    const int nx = L->nx, ny = L->ny;
+    const bool all = !has_interior(nx, ny, L->mask != nullptr);
+    const long long nb = boundary_count(nx, ny, all);
+    std::vector<unsigned> tab((size_t)nb * kQ);
+    for (long long b = 0; b < nb; ++b) {
+        int x, y;
+        boundary_site(b, nx, ny, all, x, y);
+        const long long site = (long long)y * nx + x;
+        for (int i = 0; i < kQ; ++i) {
+            const int d = i / kShells;
+            const int o = kShells * ((d + kDirs / 2) % kDirs) + (i % kShells);
+            long long sx = x - kCx[d], sy = y - kCy[d];
+            if (L->periodic_x) sx = ((sx % nx) + nx) % nx;
+            if (L->periodic_y) sy = ((sy % ny) + ny) % ny;
+            const bool inside = sx >= 0 && sx < nx && sy >= 0 && sy < ny;
+            unsigned code;
+            if (inside && !(L->mask && L->mask_host[(size_t)(sy * nx + sx)])) {
+                code = (unsigned)(i * P + sy * nx + sx);
+            } else {
+                int c = -1;
+                if (!inside) {
+                    if (sy < 0 && sx >= 0 && sx < nx) c = edge[sx];
+                    else if (sy >= ny && sx >= 0 && sx < nx) c = edge[nx + sx];
+                    else if (sx < 0 && sy >= 0 && sy < ny) c = edge[2 * nx + sy];
+                    else if (sx >= nx && sy >= 0 && sy < ny) c = edge[2 * nx + ny + sy];
+                }
+                code = c >= 0 ? (kContactFlag | (unsigned)(c * kQ + i)) : (unsigned)(o * P + site);
+            }
+            tab[(size_t)i * nb + b] = code;
+        }
+    }
+    HIP_TRY(hipMalloc((void **)&L->gtab, tab.size() * sizeof(unsigned)));
+    HIP_TRY(hipMemcpyAsync(L->gtab, tab.data(), tab.size() * sizeof(unsigned), hipMemcpyHostToDevice, L->stream));
+    HIP_TRY(hipStreamSynchronize(L->stream));
+    L->gtab_rows = nb;
+    return RLBM_OK;
+}
+
+// Upload boundary tables (when the geometry changed) and rebuild the kernel
+// argument blocks.
+rlbm_status refresh(rlbm_lattice *L, bool geometry)
 {
     const int nedge = 2 * L->nx + 2 * L->ny;
     std::vector<signed char> edge(nedge, -1);
@@ -169,6 +226,10 @@ rlbm_status refresh(rlbm_lattice *L)
         for (int p = k.start; p < k.start + k.width; ++p) edge[base + p] = (signed char)c;
     }
     HIP_TRY(hipMemcpyAsync(L->edge, edge.data(), nedge, hipMemcpyHostToDevice, L->stream));
+    if (geometry) {
+        rlbm_status gst = build_gather_table(L, edge);
+        if (gst) return gst;
+    }
     // contact equilibria in storage (eta) units
     double fref[kQ], wsc[kQ];
     host_feq(L->C.q, L->n_ref, L->T_ref, 0.0, 0.0, fref);
@@ -210,8 +271,10 @@ void set_write_fields(rlbm_lattice *L, int on)
 
 LaunchShape default_shape(int nx)
 {
-    int tx = ((nx + 63) / 64) * 64;
+    int tx = ((nx - 2 * kReach + 63) / 64) * 64;
     if (tx > 256) tx = 256;
+    if (tx < 64) tx = 64;
+    if (tx == 192) tx = 128;
     return LaunchShape{tx, 256 / tx};
 }
 
@@ -263,6 +326,7 @@ void rlbm_destroy(rlbm_lattice *L)
     hipFree(L->part);
     hipFree(L->fref);
     hipFree(L->wscale);
+    hipFree(L->gtab);
     delete L;
 }
 
@@ -285,7 +349,7 @@ rlbm_status rlbm_create(int nx, int ny, rlbm_storage storage, void *hip_stream, 
     L->ny = ny;
     L->storage = storage;
     L->stream = static_cast<hipStream_t>(hip_stream);
-    L->scale = storage == RLBM_F16DEV ? 1.0 / 256.0 : 1.0;
+    L->scale = storage == RLBM_F16DEV ? 1.0 / 4096.0 : 1.0;
     L->shape = default_shape(nx);
     const size_t P = (size_t)nx * ny;
     const size_t pop_bytes = P * kQ * store_bytes(storage);
@@ -311,7 +375,7 @@ rlbm_status rlbm_create(int nx, int ny, rlbm_storage storage, void *hip_stream, 
         return fail(e == hipErrorOutOfMemory ? RLBM_ENOMEM : RLBM_EDEVICE, "rlbm_create: %s",
                     hipGetErrorString(e));
     }
-    st = refresh(L);
+    st = refresh(L, true);
     if (st) {
         rlbm_destroy(L);
         return st;
@@ -352,7 +416,7 @@ rlbm_status rlbm_set_boundaries(rlbm_lattice *L, int periodic_x, int periodic_y,
     L->periodic_x = periodic_x != 0;
     L->periodic_y = periodic_y != 0;
     L->contacts.assign(contacts, contacts + ncontacts);
-    return refresh(L);
+    return refresh(L, true);
 }
 
 rlbm_status rlbm_set_mask(rlbm_lattice *L, const uint8_t *mask)
@@ -363,13 +427,13 @@ rlbm_status rlbm_set_mask(rlbm_lattice *L, const uint8_t *mask)
         hipFree(L->mask);
         L->mask = nullptr;
         L->mask_host.clear();
-        return refresh(L);
+        return refresh(L, true);
     }
     if (!L->mask) HIP_TRY(hipMalloc((void **)&L->mask, P));
     L->mask_host.assign(mask, mask + P);
     for (auto &v : L->mask_host) v = v ? 1 : 0;
     HIP_TRY(hipMemcpyAsync(L->mask, L->mask_host.data(), P, hipMemcpyHostToDevice, L->stream));
-    return refresh(L);
+    return refresh(L, true);
 }
 
 rlbm_status rlbm_set_tau(rlbm_lattice *L, double tau)
@@ -377,7 +441,7 @@ rlbm_status rlbm_set_tau(rlbm_lattice *L, double tau)
     CHECK_L(L);
     if (!(tau > 0.5) || !std::isfinite(tau)) return fail(RLBM_EINVAL, "rlbm_set_tau: tau must exceed 1/2 (got %g)", tau);
     L->tau = tau;
-    return refresh(L);
+    return refresh(L, false);
 }
 
 rlbm_status rlbm_set_drive(rlbm_lattice *L, double Fx, double Fy)
@@ -386,7 +450,7 @@ rlbm_status rlbm_set_drive(rlbm_lattice *L, double Fx, double Fy)
     if (!std::isfinite(Fx) || !std::isfinite(Fy)) return fail(RLBM_EINVAL, "rlbm_set_drive: non-finite force");
     L->Fx = Fx;
     L->Fy = Fy;
-    return refresh(L);
+    return refresh(L, false);
 }
 
 rlbm_status rlbm_set_reference(rlbm_lattice *L, double n_ref, double T_ref, double scale)
@@ -399,7 +463,7 @@ rlbm_status rlbm_set_reference(rlbm_lattice *L, double n_ref, double T_ref, doub
     L->scale = scale;
     L->initialized = false;
     L->fields_valid = false;
-    return refresh(L);
+    return refresh(L, false);
 }
 
 static rlbm_status do_init(rlbm_lattice *L, const double *n, const double *T, const double *vx, const double *vy,
@@ -620,7 +684,7 @@ rlbm_status rlbm_set_state(rlbm_lattice *L, const void *src, size_t bytes)
         L->n_ref = h.n_ref;
         L->T_ref = h.T_ref;
         L->scale = h.scale;
-        rlbm_status st = refresh(L);
+        rlbm_status st = refresh(L, false);
         if (st) return st;
     }
     const size_t P = (size_t)L->plane();
@@ -643,7 +707,7 @@ rlbm_status rlbm_set_state(rlbm_lattice *L, const void *src, size_t bytes)
 rlbm_status rlbm_set_launch_shape(rlbm_lattice *L, int tile_x, int rows)
 {
     CHECK_L(L);
-    if (tile_x < 64 || tile_x % 64 || rows < 1 || tile_x * rows > 256)
+    if (tile_x < 64 || tile_x % 64 || rows < 1 || tile_x * rows != 256)
         return fail(RLBM_EINVAL, "rlbm_set_launch_shape: invalid shape %d x %d", tile_x, rows);
     L->shape = LaunchShape{tile_x, rows};
     return RLBM_OK;

@@ -7,21 +7,95 @@
 
 namespace rlbm {
 
-// Non-zero positions (k, m) of C_x and C_y (Sec. 2.4 force projection,
-// b_j = C_j a): the two patterns are disjoint and together have 89 entries.
-// The host verifies at set-up that every other entry of its own C_x, C_y is
-// zero.
-constexpr int kForceNnz = 89;
-constexpr unsigned char kForceK[kForceNnz] = {
-    0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 4, 4, 4, 4, 4, 5, 5, 5, 5, 5, 5,
-    6, 6, 6, 6, 6, 6, 7, 7, 7, 7, 7, 8, 8, 8, 8, 8, 9, 9, 9, 10, 10, 10, 10, 10, 10, 10, 11, 11, 11, 11, 11, 11,
-    11, 12, 12, 12, 12, 12, 12, 12, 13, 13, 13, 13, 13, 14, 14, 15, 15, 15, 15, 15, 15, 15};
-constexpr unsigned char kForceM[kForceNnz] = {
-    2, 3, 5, 6, 10, 11, 13, 2, 3, 5, 6, 10, 11, 13, 0, 7, 8, 12, 15, 0, 7, 8, 12, 15, 5, 6, 10, 11, 13, 0, 1, 7, 8,
-    12, 15, 0, 1, 7, 8, 12, 15, 2, 3, 10, 11, 14, 2, 3, 10, 11, 14, 10, 11, 13, 0, 1, 4, 7, 8, 12, 15, 0, 1, 4, 7,
-    8, 12, 15, 2, 3, 5, 6, 10, 11, 14, 0, 1, 4, 12, 15, 7, 8, 2, 3, 5, 6, 10, 11, 14};
+// Non-zero entries {k, m, value} of the force projection matrices C_x and
+// C_y (Sec. 2.4: b_j = C_j a in the Appendix A basis).  They are fixed
+// numbers (rationals times square roots); the host recomputes both matrices
+// exactly at set-up and refuses to run if any entry differs from these or
+// if an entry outside these lists is non-zero.
+struct ForceEntry {
+    unsigned char k, m;
+    double v;
+};
+constexpr int kForceNx = 48;
+constexpr ForceEntry kForceX[kForceNx] = {
+    {0, 2, 0.5}, {0, 5, -0.57735026918962573}, {0, 10, 0.375},
+    {0, 11, 0.48412291827592713}, {1, 2, -0.5}, {1, 5, 0.57735026918962573},
+    {1, 10, -0.375}, {1, 11, -0.48412291827592713}, {2, 0, -0.5},
+    {2, 7, 0.14433756729740643}, {2, 12, -0.12909944487358058}, {3, 8, 0.14433756729740643},
+    {3, 15, -0.12909944487358058}, {4, 5, -0.57735026918962573}, {4, 10, 0.375},
+    {4, 11, 0.48412291827592713}, {5, 0, 0.28867513459481287}, {5, 1, -0.57735026918962573},
+    {5, 7, -0.25}, {5, 12, 0.22360679774997896}, {6, 8, -0.25},
+    {6, 15, 0.22360679774997896}, {7, 2, -0.4330127018922193}, {7, 10, 0.072168783648703216},
+    {7, 11, -0.055901699437494741}, {8, 3, -0.4330127018922193}, {8, 14, 0.091287092917527679},
+    {9, 10, -0.375}, {9, 11, -0.48412291827592713}, {10, 0, -0.125},
+    {10, 1, 0.25}, {10, 4, -0.375}, {10, 7, -0.36084391824351608},
+    {10, 12, -0.19364916731037085}, {11, 0, -0.1613743060919757}, {11, 1, 0.3227486121839514},
+    {11, 4, -0.48412291827592713}, {11, 7, 0.27950849718747373}, {11, 12, -0.25},
+    {12, 2, 0.19364916731037085}, {12, 5, -0.44721359549995793}, {12, 10, -0.1613743060919757},
+    {12, 11, 0.125}, {13, 15, -0.31622776601683794}, {14, 8, -0.45643546458763845},
+    {15, 3, 0.19364916731037085}, {15, 6, -0.44721359549995793}, {15, 14, -0.20412414523193151}};
+constexpr int kForceNy = 41;
+constexpr ForceEntry kForceY[kForceNy] = {
+    {0, 3, 0.5}, {0, 6, -0.57735026918962573}, {0, 13, 0.61237243569579447},
+    {1, 3, -0.5}, {1, 6, 0.57735026918962573}, {1, 13, -0.61237243569579447},
+    {2, 8, 0.14433756729740643}, {2, 15, -0.12909944487358058}, {3, 0, -0.5},
+    {3, 7, -0.14433756729740643}, {3, 12, 0.12909944487358058}, {4, 6, -0.57735026918962573},
+    {4, 13, 0.61237243569579447}, {5, 8, -0.25}, {5, 15, 0.22360679774997896},
+    {6, 0, 0.28867513459481287}, {6, 1, -0.57735026918962573}, {6, 7, 0.25},
+    {6, 12, -0.22360679774997896}, {7, 3, 0.4330127018922193}, {7, 14, 0.091287092917527679},
+    {8, 2, -0.4330127018922193}, {8, 10, -0.072168783648703216}, {8, 11, 0.055901699437494741},
+    {9, 13, -0.61237243569579447}, {10, 8, 0.36084391824351608}, {10, 15, -0.19364916731037085},
+    {11, 8, -0.27950849718747373}, {11, 15, -0.25}, {12, 3, -0.19364916731037085},
+    {12, 6, 0.44721359549995793}, {12, 14, -0.20412414523193151}, {13, 0, -0.20412414523193151},
+    {13, 1, 0.40824829046386302}, {13, 4, -0.61237243569579447}, {13, 12, 0.31622776601683794},
+    {14, 7, -0.45643546458763845}, {15, 2, 0.19364916731037085}, {15, 5, -0.44721359549995793},
+    {15, 10, 0.1613743060919757}, {15, 11, -0.125}};
+
+// The rest-frame projections of the reference state are non-zero only for
+// these Appendix A indices (J0, J1_0, J2_00, J3_000).
+constexpr int kRestK[4] = {0, 1, 4, 9};
 
 constexpr int kMaxContacts = 16;
+constexpr unsigned kContactFlag = 0x80000000u;
+
+// Boundary part of the step grid: with an interior (nx, ny > 2 * reach, no
+// mask) the bottom and top bands of `reach` rows, then the left and right
+// bands of the rows in between; without one, every site.
+__host__ __device__ inline long long boundary_count(int nx, int ny, bool all)
+{
+    if (all) return (long long)nx * ny;
+    return 2LL * kReach * nx + 2LL * kReach * (ny - 2 * kReach);
+}
+
+__host__ __device__ inline void boundary_site(long long idx, int nx, int ny, bool all, int &x, int &y)
+{
+    if (all) {
+        y = (int)(idx / nx);
+        x = (int)(idx - (long long)y * nx);
+        return;
+    }
+    const long long band = (long long)kReach * nx;
+    if (idx < band) {
+        y = (int)(idx / nx);
+        x = (int)(idx - (long long)y * nx);
+    } else if (idx < 2 * band) {
+        const long long r = idx - band;
+        const int ry = (int)(r / nx);
+        y = ny - kReach + ry;
+        x = (int)(r - (long long)ry * nx);
+    } else {
+        const long long r = idx - 2 * band;
+        const int ry = (int)(r / (2 * kReach));
+        y = kReach + ry;
+        const int c = (int)(r - (long long)ry * (2 * kReach));
+        x = c < kReach ? c : nx - 2 * kReach + c;
+    }
+}
+
+__host__ __device__ inline bool has_interior(int nx, int ny, bool mask)
+{
+    return !mask && nx > 2 * kReach && ny > 2 * kReach;
+}
 
 // Everything a step, init or decode kernel needs, passed by value.  R is the
 // arithmetic type of the population update (double for F64 storage, float
@@ -44,12 +118,17 @@ struct StepArgs {
     double a_ref[kK];  // Appendix B projections of the reference state
     double inv_scale;
     double tau_inv;
-    R cf[kForceNnz];  // (Fx C_x + Fy C_y) on the pattern
-    R cf_aref[kK];    // (Fx C_x + Fy C_y) a_ref / scale
+    R fx, fy;           // drive F (force term b = Fx C_x a + Fy C_y a, in units of scale)
+    R aref_s[4];        // a_ref[kRestK] / scale
     // boundaries
     const unsigned char *mask;        // nx*ny, 1 = solid (or null)
     const signed char *edge_contact;  // [bottom: nx][top: nx][left: ny][right: ny] -> contact or -1
     const R *contact_eta;             // [contact][48], eta units
+    // boundary gather table [48][nbnd]: source element of population i of
+    // boundary site b (plane offset included), or kContactFlag | (c*48 + i)
+    // for a contact equilibrium; null -> the gather is computed in place
+    const unsigned *gather_tab;
+    long long nbnd;
     // fields (float64 SoA), written when write_fields != 0
     double *fn, *fvx, *fvy, *feps;
 };
@@ -61,7 +140,9 @@ struct LaunchShape {
     int rows;    // rows per block
 };
 
-// One time step src -> dst (post-collision storage, pull streaming).
+// One time step src -> dst (post-collision storage, pull streaming): an
+// interior kernel for the sites whose whole stencil lies on the lattice
+// (none when there is a mask) and a boundary kernel for the rest.
 hipError_t launch_step(Store st, const void *args, const void *src, void *dst, LaunchShape shape, hipStream_t s);
 
 // Initial post-collision state from fields (n, T, vx, vy; null pointers ->

@@ -58,34 +58,42 @@ RLBM_HD constexpr DirTrig dir_trig(int d)
 template <class R>
 RLBM_HD void appendix_a_to_harmonics(const R a[kK], R H[kK])
 {
-    const R r3 = R(1.7320508075688772935274463);   // sqrt(3)
-    const R r15 = R(3.8729833462074168851792654);  // sqrt(15)
-    const R r6 = R(2.4494897427831780981972840);   // sqrt(6)
-    const R r10 = R(3.1622776601683793319988936);  // sqrt(10)
-    const R r53 = R(1.2909944487358056283930885);  // sqrt(5/3)
-    const R r23 = R(0.8164965809277260327324280);  // sqrt(2/3)
+    // constants of Appendix A, as products (no divisions in the kernels)
+    const R r3 = R(1.7320508075688772935274463);       // sqrt(3)
+    const R i3 = R(0.5773502691896257645091488);       // 1/sqrt(3)
+    const R i23 = R(0.2886751345948128822545744);      // 1/(2 sqrt(3))
+    const R h15 = R(1.9364916731037084425896327);      // sqrt(15)/2
+    const R r6 = R(2.4494897427831780981972840);       // sqrt(6)
+    const R r53 = R(1.2909944487358056283930885);      // sqrt(5/3)
+    const R h53 = R(0.6454972243679028141965442);      // sqrt(5/3)/2
+    const R r83 = R(1.6329931618554520654648560);      // 2 sqrt(2/3)
+    const R c11 = R(0.1613743060919757035491361);      // 5/(8 sqrt(15))
+    const R i26 = R(0.2041241452319315136032131);      // 1/(2 sqrt(6))
+    const R i215 = R(0.1290994448735805628393088);     // 1/(2 sqrt(15))
+    const R c14 = R(0.0322748612183951407098272);      // 1/(8 sqrt(15))
+    const R i610 = R(0.0527046276694729988666482);     // 1/(6 sqrt(10))
     // a index: 0:J0 1:J1_0 2:J1_x 3:J1_y 4:J2_00 5:J2_0x 6:J2_0y 7:J2_xx 8:J2_xy
     //          9:J3_000 10:J3_xxx 11:J3_00x 12:J3_0xx 13:J3_00y 14:J3_xxy 15:J3_0xy
     // e = 0
     H[0] = a[0] - a[1] + a[4] - a[9];
     // e = 1: [1, cos, sin]
     H[1] = a[1] - R(2) * a[4] + R(3) * a[9];
-    H[2] = a[2] - r3 * a[5] + R(1.5) * a[10] + (r15 / R(2)) * a[11];
+    H[2] = a[2] - r3 * a[5] + R(1.5) * a[10] + h15 * a[11];
     H[3] = a[3] - r3 * a[6] + r6 * a[13];
     // e = 2: [1, cos, sin, cos2, sin2]
     H[4] = R(0.5) * a[4] - R(1.5) * a[9];
-    H[5] = a[5] / r3 - a[10] - r53 * a[11];
-    H[6] = a[6] / r3 - R(2) * r23 * a[13];
-    H[7] = a[7] / (R(2) * r3) - (r53 / R(2)) * a[12];
-    H[8] = a[8] / (R(2) * r3) - (r53 / R(2)) * a[15];
+    H[5] = i3 * a[5] - a[10] - r53 * a[11];
+    H[6] = i3 * a[6] - r83 * a[13];
+    H[7] = i23 * a[7] - h53 * a[12];
+    H[8] = i23 * a[8] - h53 * a[15];
     // e = 3: [1, cos, sin, cos2, sin2, cos3, sin3]
-    H[9] = a[9] / R(6);
-    H[10] = a[10] / R(8) + (R(5) / (R(8) * r15)) * a[11];
-    H[11] = a[13] / (R(2) * r6);
-    H[12] = a[12] / (R(2) * r15);
-    H[13] = a[15] / (R(2) * r15);
-    H[14] = a[10] / R(24) - a[11] / (R(8) * r15);
-    H[15] = a[14] / (R(6) * r10);
+    H[9] = R(0.16666666666666666666666667) * a[9];
+    H[10] = R(0.125) * a[10] + c11 * a[11];
+    H[11] = i26 * a[13];
+    H[12] = i215 * a[12];
+    H[13] = i215 * a[15];
+    H[14] = R(0.04166666666666666666666667) * a[10] - c14 * a[11];
+    H[15] = i610 * a[14];
 }
 
 // Even / odd (in t -> t + pi) parts of the four radial coefficients

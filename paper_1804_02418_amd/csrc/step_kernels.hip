@@ -99,11 +99,25 @@ __device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, S
     R Ha[kK], Hb[kK];
     appendix_a_to_harmonics(ad, Ha);
     if (A.has_force) {
-        R b[kK];
+        // b = (Fx C_x + Fy C_y) a / scale with a / scale = ad + a_ref / scale
+        R as[kK];
 #pragma unroll
-        for (int k = 0; k < kK; ++k) b[k] = A.cf_aref[k];
+        for (int k = 0; k < kK; ++k) as[k] = ad[k];
 #pragma unroll
-        for (int q = 0; q < kForceNnz; ++q) b[kForceK[q]] += A.cf[q] * ad[kForceM[q]];
+        for (int r = 0; r < 4; ++r) as[kRestK[r]] += A.aref_s[r];
+        R bx[kK], by[kK], b[kK];
+#pragma unroll
+        for (int k = 0; k < kK; ++k) bx[k] = by[k] = R(0);
+        if (A.fx != R(0)) {
+#pragma unroll
+            for (int q = 0; q < kForceNx; ++q) bx[kForceX[q].k] += R(kForceX[q].v) * as[kForceX[q].m];
+        }
+        if (A.fy != R(0)) {
+#pragma unroll
+            for (int q = 0; q < kForceNy; ++q) by[kForceY[q].k] += R(kForceY[q].v) * as[kForceY[q].m];
+        }
+#pragma unroll
+        for (int k = 0; k < kK; ++k) b[k] = A.fx * bx[k] + A.fy * by[k];
         appendix_a_to_harmonics(b, Hb);
     } else {
 #pragma unroll
@@ -153,29 +167,71 @@ __device__ __forceinline__ void write_fields(const StepArgs<R> &A, long long sit
     A.feps[site] = f.eps;
 }
 
+// Gather of one site with the boundary rules: periodic wrap, then a contact's
+// ghost span (fixed equilibrium), otherwise bounce-back from the site itself
+// (also for a solid source site).
 template <class S, class R>
-__global__ __launch_bounds__(256) void step_kernel(const StepArgs<R> A, const S *__restrict__ src,
-                                                   S *__restrict__ dst)
+__device__ __forceinline__ void gather_general(const StepArgs<R> &A, const S *__restrict__ src, int x, int y,
+                                               long long site, R (&h)[kQ])
 {
-    const int tile_x = blockDim.x;
-    const int x = blockIdx.x * tile_x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int nx = A.nx, ny = A.ny;
     const long long P = A.plane;
-    const int x0 = blockIdx.x * tile_x, y0 = blockIdx.y * blockDim.y;
-    const bool interior = !A.has_mask && x0 >= kReach && x0 + tile_x + kReach <= nx && y0 >= kReach &&
-                          y0 + (int)blockDim.y + kReach <= ny;
-    if (x >= nx || y >= ny) return;
-    const long long site = (long long)y * nx + x;
-    R h[kQ];
-    if (interior) {
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            const int d = i / kShells;
-            const long long off = (long long)i * P + site - ((long long)kCy[d] * nx + kCx[d]);
-            h[i] = StoreIO<S>::template load<R>(src + off);
+    for (int i = 0; i < kQ; ++i) {
+        const int d = i / kShells;
+        const int o = kShells * ((d + kDirs / 2) % kDirs) + (i % kShells);
+        int sx = x - kCx[d], sy = y - kCy[d];
+        if (A.periodic_x) {
+            while (sx < 0) sx += nx;
+            while (sx >= nx) sx -= nx;
         }
-    } else {
+        if (A.periodic_y) {
+            while (sy < 0) sy += ny;
+            while (sy >= ny) sy -= ny;
+        }
+        const bool inside = (unsigned)sx < (unsigned)nx && (unsigned)sy < (unsigned)ny;
+        const long long s2 = (long long)sy * nx + sx;
+        const bool pull = inside && !(A.has_mask && A.mask[s2]);
+        R v;
+        if (pull) {
+            v = StoreIO<S>::template load<R>(src + (long long)i * P + s2);
+        } else {
+            int c = -1;
+            if (!inside) {
+                if (sy < 0 && (unsigned)sx < (unsigned)nx)
+                    c = A.edge_contact[sx];
+                else if (sy >= ny && (unsigned)sx < (unsigned)nx)
+                    c = A.edge_contact[nx + sx];
+                else if (sx < 0 && (unsigned)sy < (unsigned)ny)
+                    c = A.edge_contact[2 * nx + sy];
+                else if (sx >= nx && (unsigned)sy < (unsigned)ny)
+                    c = A.edge_contact[2 * nx + ny + sy];
+            }
+            v = c >= 0 ? A.contact_eta[c * kQ + i] : StoreIO<S>::template load<R>(src + (long long)o * P + site);
+        }
+        h[i] = v;
+    }
+}
+
+// One time step.  A 1-D grid of 256-thread blocks: the first nbnd blocks
+// take the boundary sites (general gather), the rest tile the interior
+// x in [5, nx - 5), y in [5, ny - 5) with tile_x * rows sites per block,
+// tiles aligned to tile_x so every wavefront stores 64 aligned values.
+// Boundary blocks come first so that they run alongside interior tiles.
+template <class S, class R>
+__global__ __launch_bounds__(256) void step_kernel(const StepArgs<R> A, const S *__restrict__ src,
+                                                   S *__restrict__ dst, int nbnd, int tile_x, int tiles_x, int all)
+{
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int nx = A.nx;
+    const long long P = A.plane;
+    int x, y;
+    R h[kQ];
+    if (b < nbnd) {
+        const long long idx = (long long)b * blockDim.x + t;
+        if (idx >= boundary_count(nx, A.ny, all)) return;
+        boundary_site(idx, nx, A.ny, all, x, y);
+        const long long site = (long long)y * nx + x;
         if (A.has_mask && A.mask[site]) {
             if (A.write_fields) {
                 A.fn[site] = 0.0;
@@ -185,44 +241,43 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs<R> A, const S 
             }
             return;
         }
+        if (A.gather_tab) {
+            const unsigned *__restrict__ tab = A.gather_tab;
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                const unsigned c = tab[(long long)i * A.nbnd + idx];
+                h[i] = (c & kContactFlag) ? A.contact_eta[c & ~kContactFlag]
+                                          : StoreIO<S>::template load<R>(src + c);
+            }
+        } else {
+            gather_general<S, R>(A, src, x, y, site, h);
+        }
+    } else {
+        const int tb = b - nbnd;
+        const int by = tb / tiles_x, bx = tb - by * tiles_x;
+        const int rows = blockDim.x / tile_x;
+        const int ty = t / tile_x;
+        x = bx * tile_x + (t - ty * tile_x);
+        y = kReach + by * rows + ty;
+        if (x < kReach || x >= nx - kReach || y >= A.ny - kReach) return;
+        // uniform plane base pointers + one 32-bit site offset
+        const unsigned site = (unsigned)y * (unsigned)nx + (unsigned)x;
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
             const int d = i / kShells;
-            const int o = 4 * ((d + kDirs / 2) % kDirs) + (i % kShells);
-            int sx = x - kCx[d], sy = y - kCy[d];
-            if (A.periodic_x && (sx < 0 || sx >= nx)) sx = ((sx % nx) + nx) % nx;
-            if (A.periodic_y && (sy < 0 || sy >= ny)) sy = ((sy % ny) + ny) % ny;
-            const bool inside = sx >= 0 && sx < nx && sy >= 0 && sy < ny;
-            R v;
-            if (inside) {
-                const long long s2 = (long long)sy * nx + sx;
-                if (A.has_mask && A.mask[s2])
-                    v = StoreIO<S>::template load<R>(src + (long long)o * P + site);
-                else
-                    v = StoreIO<S>::template load<R>(src + (long long)i * P + s2);
-            } else {
-                int c = -1;
-                if (sy < 0 && sx >= 0 && sx < nx)
-                    c = A.edge_contact[sx];
-                else if (sy >= ny && sx >= 0 && sx < nx)
-                    c = A.edge_contact[nx + sx];
-                else if (sx < 0 && sy >= 0 && sy < ny)
-                    c = A.edge_contact[2 * nx + sy];
-                else if (sx >= nx && sy >= 0 && sy < ny)
-                    c = A.edge_contact[2 * nx + ny + sy];
-                if (c >= 0)
-                    v = A.contact_eta[c * kQ + i];
-                else
-                    v = StoreIO<S>::template load<R>(src + (long long)o * P + site);
-            }
-            h[i] = v;
+            const S *__restrict__ plane = src + ((long long)i * P - ((long long)kCy[d] * nx + kCx[d]));
+            h[i] = StoreIO<S>::template load<R>(plane + site);
         }
     }
+    const unsigned site = (unsigned)y * (unsigned)nx + (unsigned)x;
     SiteFields f;
     const bool ok = collide_site<R>(h, A, f);
     if (A.write_fields) write_fields(A, site, f, ok);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) StoreIO<S>::template store<R>(dst + (long long)i * P + site, h[i]);
+    for (int i = 0; i < kQ; ++i) {
+        S *__restrict__ plane = dst + (long long)i * P;
+        StoreIO<S>::template store<R>(plane + site, h[i]);
+    }
 }
 
 template <class S, class R>
@@ -328,9 +383,18 @@ template <class S, class R>
 hipError_t launch_step_t(const void *args, const void *src, void *dst, LaunchShape sh, hipStream_t s)
 {
     const StepArgs<R> &A = *static_cast<const StepArgs<R> *>(args);
-    dim3 block(sh.tile_x, sh.rows);
-    dim3 grid((A.nx + sh.tile_x - 1) / sh.tile_x, (A.ny + sh.rows - 1) / sh.rows);
-    hipLaunchKernelGGL((step_kernel<S, R>), grid, block, 0, s, A, static_cast<const S *>(src), static_cast<S *>(dst));
+    const bool interior = !A.has_mask && A.nx > 2 * kReach && A.ny > 2 * kReach;
+    const int block = 256;
+    const long long nb = boundary_count(A.nx, A.ny, !interior);
+    const int nbnd = (int)((nb + block - 1) / block);
+    int tiles_x = 0, tiles = 0;
+    if (interior) {
+        const int rows = block / sh.tile_x;
+        tiles_x = (A.nx + sh.tile_x - 1) / sh.tile_x;
+        tiles = tiles_x * ((A.ny - 2 * kReach + rows - 1) / rows);
+    }
+    hipLaunchKernelGGL((step_kernel<S, R>), dim3((unsigned)(nbnd + tiles)), dim3(block), 0, s, A,
+                       static_cast<const S *>(src), static_cast<S *>(dst), nbnd, sh.tile_x, tiles_x, interior ? 0 : 1);
     return hipGetLastError();
 }
 
@@ -350,7 +414,7 @@ hipError_t launch_init_t(const void *args, const double *n, const double *T, con
 
 hipError_t launch_step(Store st, const void *args, const void *src, void *dst, LaunchShape shape, hipStream_t s)
 {
-    if (shape.tile_x <= 0 || shape.rows <= 0 || shape.tile_x * shape.rows > 256 || shape.tile_x % 64)
+    if (shape.tile_x <= 0 || shape.rows <= 0 || shape.tile_x * shape.rows != 256 || shape.tile_x % 64)
         return hipErrorInvalidValue;
     switch (st) {
     case Store::F64: return launch_step_t<double, double>(args, src, dst, shape, s);

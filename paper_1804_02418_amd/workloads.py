@@ -83,10 +83,13 @@ def small_device(nx: int = 203, ny: int = 77, steps: int = 120, seed: int = 5):
     T = 1 + 0.01 * np.cos(2 * np.pi * x / nx + ph[2])
     vx = 0.01 * np.sin(2 * np.pi * y / ny + ph[3])
     vy = 0.005 * np.cos(2 * np.pi * x / nx)
-    contacts = [dict(edge="bottom", start=30, width=25, n=1.02, T=1.0),
-                dict(edge="bottom", start=140, width=40, n=0.99, T=1.01, vx=0.002),
-                dict(edge="top", start=0, width=17, n=1.0, T=0.98),
-                dict(edge="left", start=20, width=30, n=1.01, T=1.0, vx=0.003, vy=-0.001)]
+    # contact spans scale with the lattice (203 x 77: bottom [30, 54) and
+    # [140, 180), top [0, 16), left [20, 50))
+    contacts = [dict(edge="bottom", start=int(0.15 * nx), width=max(1, int(0.12 * nx)), n=1.02, T=1.0),
+                dict(edge="bottom", start=int(0.69 * nx), width=max(1, int(0.2 * nx)), n=0.99, T=1.01, vx=0.002),
+                dict(edge="top", start=0, width=max(1, int(0.08 * nx)), n=1.0, T=0.98),
+                dict(edge="left", start=int(0.26 * ny), width=max(1, int(0.39 * ny)), n=1.01, T=1.0, vx=0.003,
+                     vy=-0.001)]
     return dict(name=f"small_device_{nx}x{ny}", nx=nx, ny=ny, periodic_x=False, periodic_y=False,
                 contacts=contacts, tau=0.75, F=(2e-4, -1e-4), steps=steps, storage="f64",
                 init=dict(n=n, T=T, vx=vx, vy=vy))
