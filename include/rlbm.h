@@ -192,8 +192,79 @@ rlbm_status rlbm_set_state(rlbm_lattice *lat, const void *src, size_t bytes);
  * to 64. */
 rlbm_status rlbm_set_launch_shape(rlbm_lattice *lat, int tile_x, int rows);
 
+/* Autotuner: time every candidate launch shape of the step kernel on this
+ * lattice (trial_steps timed steps each, after 2 warm-up steps, with HIP
+ * events on the lattice's stream), keep the fastest, and remember it for
+ * lattices of the same device architecture, storage, size and mask use in
+ * this process (and in the text file named by the environment variable
+ * RLBM_TUNE_CACHE, if set, which later processes read at rlbm_create).  The
+ * lattice state, time and fields are restored afterwards.  ms_per_step
+ * (optional, 3 entries, caller-owned) receives the timings of tile_x = 64,
+ * 128, 256 (0 for a shape that does not apply).  Synchronises. */
+rlbm_status rlbm_autotune(rlbm_lattice *lat, int trial_steps, double *ms_per_step);
+
 /* Block until all work queued on the lattice's stream is done. */
 rlbm_status rlbm_synchronize(rlbm_lattice *lat);
+
+/* ---- many lattices in one launch ---- */
+
+typedef struct rlbm_batch rlbm_batch;
+
+/* One sample of a batch: its own lattice size, boundaries (up to 4
+ * contacts), tau, drive and uniform initial state. */
+typedef struct {
+    int nx, ny;
+    int periodic_x, periodic_y;
+    double tau, Fx, Fy;
+    int ncontacts;
+    rlbm_contact contacts[4];
+    double n0, T0, vx0, vy0;
+} rlbm_sample;
+
+/* Create a batch of nsamples (>= 1) lattices with one storage, all ordered
+ * on one stream (hip_stream, or a stream the batch creates when NULL), and
+ * initialise each to its uniform equilibrium.  The samples may differ in
+ * size and parameters. */
+rlbm_status rlbm_batch_create(const rlbm_sample *samples, int nsamples, rlbm_storage storage, void *hip_stream,
+                              rlbm_batch **out);
+
+/* Release the batch and all its lattices.  NULL is a no-op. */
+void rlbm_batch_destroy(rlbm_batch *b);
+
+/* The lattice of sample i (owned by the batch): every single-lattice call
+ * (fields, residual, init for warm starts, checkpoints, ...) works on it. */
+rlbm_status rlbm_batch_lattice(rlbm_batch *b, int i, rlbm_lattice **lat);
+
+/* Advance every active sample by nsteps.  Each step is ONE launch of a
+ * persistent kernel whose blocks drain the (sample, block) work items of all
+ * active samples through an atomic queue; with use_graph the launches are
+ * replayed from a captured HIP graph.  Fields are kept for the last step. */
+rlbm_status rlbm_batch_step(rlbm_batch *b, int64_t nsteps, int use_graph);
+
+/* Mark samples active (1) or frozen (0); frozen samples keep their state
+ * and take no work.  active: nsamples bytes, caller-owned. */
+rlbm_status rlbm_batch_set_active(rlbm_batch *b, const uint8_t *active);
+
+/* Residual of every sample over its last rlbm_batch_step call (as
+ * rlbm_residual), in one batched reduction; r has nsamples entries
+ * (caller-owned).  RLBM_EUNSTABLE if any sample fails the health check. */
+rlbm_status rlbm_batch_residual(rlbm_batch *b, double *r);
+
+/* Step until every sample's residual over check_every steps is below tol or
+ * max_steps have been taken; converged samples are frozen as they converge.
+ * steps[i] receives the steps sample i took, r[i] its last residual (both
+ * caller-owned, nsamples entries, may be NULL). */
+rlbm_status rlbm_batch_step_until(rlbm_batch *b, int64_t max_steps, int64_t check_every, double tol,
+                                  int64_t *steps, double *r);
+
+/* Autotuner for the batch: time the batched step with every sample's tile
+ * width set to each candidate (64, 128, 256, capped at the sample's interior
+ * width), keep the fastest, restore all states.  ms_per_step: 3 entries or
+ * NULL. */
+rlbm_status rlbm_batch_autotune(rlbm_batch *b, int trial_steps, double *ms_per_step);
+
+/* Total lattice sites of the active samples. */
+rlbm_status rlbm_batch_sites(rlbm_batch *b, int64_t *sites);
 
 #ifdef __cplusplus
 }

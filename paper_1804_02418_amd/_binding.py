@@ -31,6 +31,20 @@ class rlbm_contact(ctypes.Structure):
                 ("n", ctypes.c_double), ("T", ctypes.c_double), ("vx", ctypes.c_double), ("vy", ctypes.c_double)]
 
 
+class rlbm_sample(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("periodic_x", ctypes.c_int), ("periodic_y", ctypes.c_int),
+                ("tau", ctypes.c_double), ("Fx", ctypes.c_double), ("Fy", ctypes.c_double),
+                ("ncontacts", ctypes.c_int), ("contacts", rlbm_contact * 4),
+                ("n0", ctypes.c_double), ("T0", ctypes.c_double), ("vx0", ctypes.c_double), ("vy0", ctypes.c_double)]
+
+
+def _contact(c) -> rlbm_contact:
+    e = c["edge"]
+    return rlbm_contact(EDGE.get(e, e) if isinstance(e, str) else int(e), int(c["start"]), int(c["width"]),
+                        float(c.get("n", 1.0)), float(c.get("T", 1.0)), float(c.get("vx", 0.0)),
+                        float(c.get("vy", 0.0)))
+
+
 _lib = None
 
 _vp = ctypes.c_void_p
@@ -62,7 +76,17 @@ SIGNATURES = {
     "rlbm_get_state": ([_vp, _vp, ctypes.c_size_t], None),
     "rlbm_set_state": ([_vp, _vp, ctypes.c_size_t], None),
     "rlbm_set_launch_shape": ([_vp, ctypes.c_int, ctypes.c_int], None),
+    "rlbm_autotune": ([_vp, ctypes.c_int, _dp], None),
     "rlbm_synchronize": ([_vp], None),
+    "rlbm_batch_create": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)], None),
+    "rlbm_batch_destroy": ([_vp], "void"),
+    "rlbm_batch_lattice": ([_vp, ctypes.c_int, ctypes.POINTER(_vp)], None),
+    "rlbm_batch_step": ([_vp, _i64, ctypes.c_int], None),
+    "rlbm_batch_set_active": ([_vp, _vp], None),
+    "rlbm_batch_residual": ([_vp, _dp], None),
+    "rlbm_batch_step_until": ([_vp, _i64, _i64, ctypes.c_double, _vp, _dp], None),
+    "rlbm_batch_autotune": ([_vp, ctypes.c_int, _dp], None),
+    "rlbm_batch_sites": ([_vp, ctypes.POINTER(_i64)], None),
 }
 
 
@@ -142,10 +166,7 @@ class Lattice:
         contacts = list(contacts)
         arr = (rlbm_contact * max(1, len(contacts)))()
         for k, c in enumerate(contacts):
-            e = c["edge"]
-            arr[k] = rlbm_contact(EDGE.get(e, e) if isinstance(e, str) else int(e), int(c["start"]),
-                                  int(c["width"]), float(c.get("n", 1.0)), float(c.get("T", 1.0)),
-                                  float(c.get("vx", 0.0)), float(c.get("vy", 0.0)))
+            arr[k] = _contact(c)
         check(lib().rlbm_set_boundaries(self._h, int(bool(periodic_x)), int(bool(periodic_y)), arr, len(contacts)))
 
     def set_mask(self, mask):
@@ -228,5 +249,97 @@ class Lattice:
     def set_launch_shape(self, tile_x: int, rows: int):
         check(lib().rlbm_set_launch_shape(self._h, int(tile_x), int(rows)))
 
+    def autotune(self, trial_steps: int = 20):
+        """Pick the fastest launch shape; returns ms/step for tile_x 64, 128, 256."""
+        ms = np.zeros(3)
+        check(lib().rlbm_autotune(self._h, int(trial_steps), ms.ctypes.data_as(_dp)))
+        return ms
+
     def synchronize(self):
         check(lib().rlbm_synchronize(self._h))
+
+
+class _BorrowedLattice(Lattice):
+    """A sample lattice owned by a Batch (not destroyed from Python)."""
+
+    def __init__(self, handle, nx, ny, storage):
+        self.nx, self.ny, self.storage, self._h = nx, ny, storage, handle
+
+    def close(self) -> None:
+        self._h = None
+
+
+class Batch:
+    """Many uneven lattices advanced together by the batched persistent
+    kernel (see rlbm_batch_* in include/rlbm.h)."""
+
+    def __init__(self, samples, storage="f32", stream=None):
+        n = len(samples)
+        arr = (rlbm_sample * n)()
+        for k, w in enumerate(samples):
+            cs = list(w["contacts"])
+            if len(cs) > 4:
+                raise ValueError("at most 4 contacts per sample")
+            q = arr[k]
+            q.nx, q.ny = int(w["nx"]), int(w["ny"])
+            q.periodic_x, q.periodic_y = int(bool(w["periodic_x"])), int(bool(w["periodic_y"]))
+            q.tau, q.Fx, q.Fy = float(w["tau"]), float(w["F"][0]), float(w["F"][1])
+            q.ncontacts = len(cs)
+            for j, c in enumerate(cs):
+                q.contacts[j] = _contact(c)
+            i = w.get("init", {})
+            q.n0, q.T0 = float(i.get("n", 1.0)), float(i.get("T", 1.0))
+            q.vx0, q.vy0 = float(i.get("vx", 0.0)), float(i.get("vy", 0.0))
+        self.storage = STORAGE[storage]
+        self.n = n
+        h = _vp()
+        s = _vp(stream) if stream is not None else None
+        check(lib().rlbm_batch_create(arr, n, self.storage, s, ctypes.byref(h)))
+        self._h = h
+        self.lattices = []
+        for k in range(n):
+            lh = _vp()
+            check(lib().rlbm_batch_lattice(self._h, k, ctypes.byref(lh)))
+            self.lattices.append(_BorrowedLattice(lh, arr[k].nx, arr[k].ny, self.storage))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            for L in self.lattices:
+                L.close()
+            lib().rlbm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, nsteps: int, graph: bool = True):
+        check(lib().rlbm_batch_step(self._h, int(nsteps), int(bool(graph))))
+
+    def set_active(self, active):
+        a = np.ascontiguousarray(active, dtype=np.uint8)
+        check(lib().rlbm_batch_set_active(self._h, a.ctypes.data))
+
+    def residual(self) -> np.ndarray:
+        r = np.zeros(self.n)
+        check(lib().rlbm_batch_residual(self._h, r.ctypes.data_as(_dp)))
+        return r
+
+    def step_until(self, max_steps: int, check_every: int, tol: float):
+        steps = np.zeros(self.n, dtype=np.int64)
+        r = np.zeros(self.n)
+        check(lib().rlbm_batch_step_until(self._h, int(max_steps), int(check_every), float(tol), steps.ctypes.data,
+                                          r.ctypes.data_as(_dp)))
+        return steps, r
+
+    def autotune(self, trial_steps: int = 10) -> np.ndarray:
+        ms = np.zeros(3)
+        check(lib().rlbm_batch_autotune(self._h, int(trial_steps), ms.ctypes.data_as(_dp)))
+        return ms
+
+    def sites(self) -> int:
+        n = _i64()
+        check(lib().rlbm_batch_sites(self._h, ctypes.byref(n)))
+        return n.value

@@ -5,8 +5,12 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -19,6 +23,9 @@ using namespace rlbm;
 namespace {
 
 thread_local std::string g_error;
+
+// release paths ignore HIP errors on purpose (nothing useful can be done)
+inline void dfree(void *p) { (void)hipFree(p); }
 
 rlbm_status fail(rlbm_status st, const char *fmt, ...)
 {
@@ -169,7 +176,7 @@ void fill_args(rlbm_lattice *L, StepArgs<R> &A)
 // equilibrium.  Used while 48 * nx * ny fits in 31 bits.
 rlbm_status build_gather_table(rlbm_lattice *L, const std::vector<signed char> &edge)
 {
-    hipFree(L->gtab);
+    dfree(L->gtab);
     L->gtab = nullptr;
     L->gtab_rows = 0;
     const long long P = L->plane();
@@ -269,6 +276,49 @@ void set_write_fields(rlbm_lattice *L, int on)
     L->args_f.write_fields = on;
 }
 
+// ---- autotune cache: (arch, storage, nx, ny, mask) -> tile_x ----
+using TuneKey = std::tuple<std::string, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+void tune_cache_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("RLBM_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char arch[64];
+    int st, nx, ny, mask, tile;
+    while (std::fscanf(f, "%63s %d %d %d %d %d", arch, &st, &nx, &ny, &mask, &tile) == 6)
+        g_tune[TuneKey(arch, st, nx, ny, mask)] = tile;
+    std::fclose(f);
+}
+
+void tune_cache_store(const TuneKey &k, int tile)
+{
+    g_tune[k] = tile;
+    const char *path = std::getenv("RLBM_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d %d\n", std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                 std::get<4>(k), tile);
+    std::fclose(f);
+}
+
 LaunchShape default_shape(int nx)
 {
     int tx = ((nx - 2 * kReach + 63) / 64) * 64;
@@ -316,17 +366,17 @@ void rlbm_destroy(rlbm_lattice *L)
 {
     if (!L) return;
     (void)hipStreamSynchronize(L->stream);
-    hipFree(L->pop[0]);
-    hipFree(L->pop[1]);
-    hipFree(L->fld);
-    hipFree(L->prev);
-    hipFree(L->mask);
-    hipFree(L->edge);
-    hipFree(L->contact_eta);
-    hipFree(L->part);
-    hipFree(L->fref);
-    hipFree(L->wscale);
-    hipFree(L->gtab);
+    dfree(L->pop[0]);
+    dfree(L->pop[1]);
+    dfree(L->fld);
+    dfree(L->prev);
+    dfree(L->mask);
+    dfree(L->edge);
+    dfree(L->contact_eta);
+    dfree(L->part);
+    dfree(L->fref);
+    dfree(L->wscale);
+    dfree(L->gtab);
     delete L;
 }
 
@@ -351,6 +401,12 @@ rlbm_status rlbm_create(int nx, int ny, rlbm_storage storage, void *hip_stream, 
     L->stream = static_cast<hipStream_t>(hip_stream);
     L->scale = storage == RLBM_F16DEV ? 1.0 / 4096.0 : 1.0;
     L->shape = default_shape(nx);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_load();
+        auto it = g_tune.find(TuneKey(device_arch(), (int)storage, nx, ny, 0));
+        if (it != g_tune.end()) L->shape = LaunchShape{it->second, 256 / it->second};
+    }
     const size_t P = (size_t)nx * ny;
     const size_t pop_bytes = P * kQ * store_bytes(storage);
     L->part_blocks = (int)std::min<size_t>(1024, (P + 255) / 256);
@@ -424,7 +480,7 @@ rlbm_status rlbm_set_mask(rlbm_lattice *L, const uint8_t *mask)
     CHECK_L(L);
     const size_t P = (size_t)L->plane();
     if (!mask) {
-        hipFree(L->mask);
+        dfree(L->mask);
         L->mask = nullptr;
         L->mask_host.clear();
         return refresh(L, true);
@@ -622,7 +678,7 @@ rlbm_status rlbm_read_populations(rlbm_lattice *L, double *f, int on_device)
     hipError_t e = launch_decode(L->store(), L->nx, L->ny, L->pop[L->cur], L->fref, L->wscale, tmp, L->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(f, tmp, bytes, hipMemcpyDeviceToHost, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
-    hipFree(tmp);
+    dfree(tmp);
     if (e != hipSuccess) return fail(RLBM_EDEVICE, "rlbm_read_populations: %s", hipGetErrorString(e));
     return RLBM_OK;
 }
@@ -713,11 +769,502 @@ rlbm_status rlbm_set_launch_shape(rlbm_lattice *L, int tile_x, int rows)
     return RLBM_OK;
 }
 
+rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
+{
+    CHECK_L(L);
+    if (!L->initialized) return fail(RLBM_ESTATE, "rlbm_autotune: lattice not initialised");
+    if (trial_steps < 1) return fail(RLBM_EINVAL, "rlbm_autotune: trial_steps must be >= 1");
+    const size_t P = (size_t)L->plane();
+    const size_t pb = P * kQ * store_bytes(L->storage);
+    // save the state (current populations, fields, previous velocities)
+    void *save = nullptr;
+    HIP_TRY(hipMalloc(&save, pb + 6 * P * sizeof(double)));
+    char *sv = static_cast<char *>(save);
+    const int cur0 = L->cur;
+    const int64_t t0 = L->t, k0 = L->last_K;
+    const bool fv0 = L->fields_valid;
+    const LaunchShape shape0 = L->shape;
+    hipError_t e = hipMemcpyAsync(sv, L->pop[cur0], pb, hipMemcpyDeviceToDevice, L->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(sv + pb, L->fld, 4 * P * sizeof(double), hipMemcpyDeviceToDevice, L->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sv + pb + 4 * P * sizeof(double), L->prev, 2 * P * sizeof(double), hipMemcpyDeviceToDevice,
+                           L->stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const int tiles[3] = {64, 128, 256};
+    double best = INFINITY;
+    int best_tile = shape0.tile_x;
+    const int interior_w = L->nx - 2 * kReach;
+    for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+        if (ms_per_step) ms_per_step[c] = 0.0;
+        if (c > 0 && tiles[c - 1] >= interior_w) continue;  // wider tiles only add idle lanes
+        L->shape = LaunchShape{tiles[c], 256 / tiles[c]};
+        rlbm_status st = rlbm_step(L, 2);
+        if (st == RLBM_OK) e = hipEventRecord(e0, L->stream);
+        if (st == RLBM_OK && e == hipSuccess) st = rlbm_step(L, trial_steps);
+        if (st == RLBM_OK && e == hipSuccess) e = hipEventRecord(e1, L->stream);
+        if (st == RLBM_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (st == RLBM_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (st != RLBM_OK) {
+            e = hipErrorUnknown;
+            break;
+        }
+        const double per = ms / trial_steps;
+        if (ms_per_step) ms_per_step[c] = per;
+        if (per < best) {
+            best = per;
+            best_tile = tiles[c];
+        }
+    }
+    // restore
+    L->cur = cur0;
+    if (e == hipSuccess) e = hipMemcpyAsync(L->pop[cur0], sv, pb, hipMemcpyDeviceToDevice, L->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(L->fld, sv + pb, 4 * P * sizeof(double), hipMemcpyDeviceToDevice, L->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(L->prev, sv + pb + 4 * P * sizeof(double), 2 * P * sizeof(double), hipMemcpyDeviceToDevice,
+                           L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    dfree(save);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    L->t = t0;
+    L->last_K = k0;
+    L->fields_valid = fv0;
+    if (e != hipSuccess) {
+        L->shape = shape0;
+        return fail(RLBM_EDEVICE, "rlbm_autotune: %s", hipGetErrorString(e));
+    }
+    L->shape = LaunchShape{best_tile, 256 / best_tile};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_store(TuneKey(device_arch(), (int)L->storage, L->nx, L->ny, L->mask ? 1 : 0), best_tile);
+    return RLBM_OK;
+}
+
 rlbm_status rlbm_synchronize(rlbm_lattice *L)
 {
     CHECK_L(L);
     HIP_TRY(hipStreamSynchronize(L->stream));
     return RLBM_OK;
+}
+
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batch
+
+struct rlbm_batch {
+    std::vector<rlbm_lattice *> lat;
+    std::vector<uint8_t> active;
+    rlbm_storage storage = RLBM_F64;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void *descs = nullptr;      // BatchDesc<R>[n]
+    unsigned *items = nullptr;  // work list
+    size_t items_cap = 0;
+    int *n_items = nullptr;
+    int n_items_host = 0;
+    unsigned *counters = nullptr;
+    double *part = nullptr;
+    int part_blocks = 0;
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    static constexpr int kGraphSteps = 32;
+};
+
+namespace {
+
+int step_blocks(const rlbm_lattice *L, int *nbnd, int *tiles_x, int *all)
+{
+    const bool interior = has_interior(L->nx, L->ny, L->mask != nullptr);
+    *all = interior ? 0 : 1;
+    const long long nb = boundary_count(L->nx, L->ny, !interior);
+    *nbnd = (int)((nb + 255) / 256);
+    *tiles_x = 0;
+    int tiles = 0;
+    if (interior) {
+        const int rows = 256 / L->shape.tile_x;
+        *tiles_x = (L->nx + L->shape.tile_x - 1) / L->shape.tile_x;
+        tiles = *tiles_x * ((L->ny - 2 * kReach + rows - 1) / rows);
+    }
+    return *nbnd + tiles;
+}
+
+template <class R>
+rlbm_status upload_descs_t(rlbm_batch *B)
+{
+    const int n = (int)B->lat.size();
+    std::vector<BatchDesc<R>> d(n);
+    std::vector<unsigned> items;
+    for (int s = 0; s < n; ++s) {
+        rlbm_lattice *L = B->lat[s];
+        BatchDesc<R> &D = d[s];
+        D.a = *static_cast<const StepArgs<R> *>(L->args());
+        D.a.write_fields = 0;
+        D.pop[0] = L->pop[0];
+        D.pop[1] = L->pop[1];
+        D.pvx = L->prev;
+        D.pvy = L->prev + L->plane();
+        const int nblk = step_blocks(L, &D.nbnd, &D.tiles_x, &D.all);
+        D.tile_x = L->shape.tile_x;
+        D.parity_xor = L->cur;  // launches start at parity 0
+        D.pad_ = 0;
+        if (!B->active[s]) continue;
+        for (int b = 0; b < nblk; ++b) items.push_back(((unsigned)s << kItemBlockBits) | (unsigned)b);
+    }
+    HIP_TRY(hipMemcpyAsync(B->descs, d.data(), n * sizeof(BatchDesc<R>), hipMemcpyHostToDevice, B->stream));
+    if (items.size() > B->items_cap) {
+        dfree(B->items);
+        B->items = nullptr;
+        HIP_TRY(hipMalloc((void **)&B->items, items.size() * sizeof(unsigned)));
+        B->items_cap = items.size();
+    }
+    if (!items.empty())
+        HIP_TRY(hipMemcpyAsync(B->items, items.data(), items.size() * sizeof(unsigned), hipMemcpyHostToDevice,
+                               B->stream));
+    B->n_items_host = (int)items.size();
+    HIP_TRY(hipMemcpyAsync(B->n_items, &B->n_items_host, sizeof(int), hipMemcpyHostToDevice, B->stream));
+    HIP_TRY(hipStreamSynchronize(B->stream));  // host vectors go out of scope
+    return RLBM_OK;
+}
+
+rlbm_status upload_descs(rlbm_batch *B)
+{
+    return B->storage == RLBM_F64 ? upload_descs_t<double>(B) : upload_descs_t<float>(B);
+}
+
+Store store_of(rlbm_storage st) { return st == RLBM_F64 ? Store::F64 : st == RLBM_F32 ? Store::F32 : Store::F16; }
+
+rlbm_status batch_launch(rlbm_batch *B, int parity, int wf)
+{
+    HIP_TRY(launch_batch_step(store_of(B->storage), B->descs, B->items, B->n_items, B->counters, B->grid, parity, wf,
+                              B->stream));
+    return RLBM_OK;
+}
+
+rlbm_status ensure_graph(rlbm_batch *B)
+{
+    if (B->exec) return RLBM_OK;
+    HIP_TRY(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
+    rlbm_status st = RLBM_OK;
+    for (int k = 0; k < rlbm_batch::kGraphSteps && st == RLBM_OK; ++k) st = batch_launch(B, k & 1, 0);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(B->stream, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(RLBM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    B->graph = g;
+    HIP_TRY(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    return RLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rlbm_batch_destroy(rlbm_batch *B)
+{
+    if (!B) return;
+    if (B->stream) (void)hipStreamSynchronize(B->stream);
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    for (rlbm_lattice *L : B->lat) rlbm_destroy(L);
+    dfree(B->descs);
+    dfree(B->items);
+    dfree(B->n_items);
+    dfree(B->counters);
+    dfree(B->part);
+    if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
+    delete B;
+}
+
+rlbm_status rlbm_batch_create(const rlbm_sample *samples, int nsamples, rlbm_storage storage, void *hip_stream,
+                              rlbm_batch **out)
+{
+    if (!out) return fail(RLBM_EINVAL, "rlbm_batch_create: out is NULL");
+    *out = nullptr;
+    if (!samples || nsamples < 1 || nsamples >= (1 << (32 - kItemBlockBits)))
+        return fail(RLBM_EINVAL, "rlbm_batch_create: invalid sample count %d", nsamples);
+    rlbm_batch *B = new (std::nothrow) rlbm_batch();
+    if (!B) return fail(RLBM_ENOMEM, "rlbm_batch_create: host allocation failed");
+    B->storage = storage;
+    if (hip_stream) {
+        B->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&B->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete B;
+            return fail(RLBM_EDEVICE, "rlbm_batch_create: %s", hipGetErrorString(e));
+        }
+        B->own_stream = true;
+    }
+    rlbm_status st = RLBM_OK;
+    for (int s = 0; s < nsamples && st == RLBM_OK; ++s) {
+        const rlbm_sample &q = samples[s];
+        if (q.ncontacts < 0 || q.ncontacts > 4) {
+            st = fail(RLBM_EINVAL, "sample %d: at most 4 contacts", s);
+            break;
+        }
+        rlbm_lattice *L = nullptr;
+        st = rlbm_create(q.nx, q.ny, storage, B->stream, &L);
+        if (st) break;
+        B->lat.push_back(L);
+        int nblk_dummy[3];
+        if (step_blocks(L, &nblk_dummy[0], &nblk_dummy[1], &nblk_dummy[2]) >= (1 << kItemBlockBits)) {
+            st = fail(RLBM_EINVAL, "sample %d is too large for the batched work list", s);
+            break;
+        }
+        st = rlbm_set_boundaries(L, q.periodic_x, q.periodic_y, q.contacts, q.ncontacts);
+        if (!st) st = rlbm_set_tau(L, q.tau);
+        if (!st) st = rlbm_set_drive(L, q.Fx, q.Fy);
+        if (!st) st = rlbm_init_uniform(L, q.n0, q.T0, q.vx0, q.vy0);
+        if (st) g_error = "sample " + std::to_string(s) + ": " + g_error;
+    }
+    B->active.assign(nsamples, 1);
+    const size_t desc_bytes = nsamples * (storage == RLBM_F64 ? sizeof(BatchDesc<double>) : sizeof(BatchDesc<float>));
+    hipError_t e = hipSuccess;
+    if (!st) e = hipMalloc(&B->descs, desc_bytes);
+    if (!st && e == hipSuccess) e = hipMalloc((void **)&B->n_items, sizeof(int));
+    if (!st && e == hipSuccess) e = hipMalloc((void **)&B->counters, 2 * sizeof(unsigned));
+    if (!st && e == hipSuccess) e = hipMemsetAsync(B->counters, 0, 2 * sizeof(unsigned), B->stream);
+    B->part_blocks = 8;
+    if (!st && e == hipSuccess) e = hipMalloc((void **)&B->part, (size_t)nsamples * B->part_blocks * 3 * sizeof(double));
+    if (!st && e != hipSuccess) st = fail(RLBM_EDEVICE, "rlbm_batch_create: %s", hipGetErrorString(e));
+    if (!st) {
+        B->grid = batch_resident_blocks(store_of(storage));
+        if (B->grid <= 0) st = fail(RLBM_EDEVICE, "rlbm_batch_create: occupancy query failed");
+    }
+    if (!st) st = upload_descs(B);
+    if (st) {
+        rlbm_batch_destroy(B);
+        return st;
+    }
+    *out = B;
+    return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_lattice(rlbm_batch *B, int i, rlbm_lattice **lat)
+{
+    if (!B || !lat || i < 0 || i >= (int)B->lat.size()) return fail(RLBM_EINVAL, "rlbm_batch_lattice: bad argument");
+    *lat = B->lat[i];
+    return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_sites(rlbm_batch *B, int64_t *sites)
+{
+    if (!B || !sites) return fail(RLBM_EINVAL, "rlbm_batch_sites: bad argument");
+    int64_t n = 0;
+    for (size_t s = 0; s < B->lat.size(); ++s)
+        if (B->active[s]) n += B->lat[s]->plane();
+    *sites = n;
+    return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_set_active(rlbm_batch *B, const uint8_t *active)
+{
+    if (!B || !active) return fail(RLBM_EINVAL, "rlbm_batch_set_active: bad argument");
+    for (size_t s = 0; s < B->lat.size(); ++s) B->active[s] = active[s] ? 1 : 0;
+    return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_step(rlbm_batch *B, int64_t nsteps, int use_graph)
+{
+    if (!B) return fail(RLBM_EINVAL, "rlbm_batch_step: NULL batch");
+    if (nsteps < 0) return fail(RLBM_EINVAL, "rlbm_batch_step: negative step count");
+    if (nsteps == 0) return RLBM_OK;
+    // descriptors reflect each sample's current buffer, shape and parameters
+    rlbm_status st = upload_descs(B);
+    if (st) return st;
+    for (size_t s = 0; s < B->lat.size(); ++s) {
+        rlbm_lattice *L = B->lat[s];
+        if (!B->active[s]) continue;
+        if (!L->initialized) return fail(RLBM_ESTATE, "rlbm_batch_step: sample %zu not initialised", s);
+        HIP_TRY(hipMemcpyAsync(L->prev, L->fld + L->plane(), 2 * L->plane() * sizeof(double), hipMemcpyDeviceToDevice,
+                               B->stream));
+    }
+    if (B->n_items_host > 0) {
+        int64_t done = 0;
+        const int64_t body = nsteps - 1;  // the last step writes fields
+        if (use_graph && body >= rlbm_batch::kGraphSteps) {
+            st = ensure_graph(B);
+            if (st) return st;
+            for (; done + rlbm_batch::kGraphSteps <= body; done += rlbm_batch::kGraphSteps)
+                HIP_TRY(hipGraphLaunch(B->exec, B->stream));
+        }
+        for (; done < body; ++done) {
+            st = batch_launch(B, (int)(done & 1), 0);
+            if (st) return st;
+        }
+        st = batch_launch(B, (int)(done & 1), 1);
+        if (st) return st;
+    }
+    for (size_t s = 0; s < B->lat.size(); ++s) {
+        if (!B->active[s]) continue;
+        rlbm_lattice *L = B->lat[s];
+        L->cur ^= (int)(nsteps & 1);
+        L->t += nsteps;
+        L->last_K = nsteps;
+        L->fields_valid = true;
+    }
+    return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_residual(rlbm_batch *B, double *r)
+{
+    if (!B || !r) return fail(RLBM_EINVAL, "rlbm_batch_residual: bad argument");
+    const int n = (int)B->lat.size();
+    HIP_TRY(launch_batch_residual(store_of(B->storage), B->descs, n, B->part_blocks, B->part, B->stream));
+    std::vector<double> h((size_t)n * B->part_blocks * 3);
+    HIP_TRY(hipMemcpyAsync(h.data(), B->part, h.size() * sizeof(double), hipMemcpyDeviceToHost, B->stream));
+    HIP_TRY(hipStreamSynchronize(B->stream));
+    double bad_total = 0;
+    for (int s = 0; s < n; ++s) {
+        double dv = 0, vv = 0, bad = 0;
+        for (int j = 0; j < B->part_blocks; ++j) {
+            const double *p = &h[((size_t)s * B->part_blocks + j) * 3];
+            dv += p[0];
+            vv += p[1];
+            bad += p[2];
+        }
+        const double K = B->lat[s]->last_K > 0 ? (double)B->lat[s]->last_K : 1.0;
+        r[s] = vv > 0 ? std::sqrt(dv) / (K * std::sqrt(vv)) : 0.0;
+        bad_total += bad;
+    }
+    if (bad_total > 0) return fail(RLBM_EUNSTABLE, "health check: %.0f unhealthy sites in the batch", bad_total);
+    return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_step_until(rlbm_batch *B, int64_t max_steps, int64_t check_every, double tol, int64_t *steps,
+                                  double *r)
+{
+    if (!B || check_every < 1 || max_steps < 0) return fail(RLBM_EINVAL, "rlbm_batch_step_until: bad argument");
+    const int n = (int)B->lat.size();
+    std::vector<int64_t> taken(n, 0);
+    std::vector<double> res(n, INFINITY), cur(n);
+    std::vector<uint8_t> act = B->active;
+    int64_t done = 0;
+    rlbm_status st = RLBM_OK;
+    while (done < max_steps) {
+        bool any = false;
+        for (int s = 0; s < n; ++s) any = any || act[s];
+        if (!any) break;
+        const int64_t k = std::min<int64_t>(check_every, max_steps - done);
+        rlbm_batch_set_active(B, act.data());
+        st = rlbm_batch_step(B, k, 1);
+        if (st) break;
+        done += k;
+        st = rlbm_batch_residual(B, cur.data());
+        for (int s = 0; s < n; ++s) {
+            if (!act[s]) continue;
+            taken[s] += k;
+            res[s] = cur[s];
+            if (k == check_every && cur[s] < tol) act[s] = 0;
+        }
+        if (st) break;
+    }
+    std::vector<uint8_t> all(n, 1);
+    rlbm_batch_set_active(B, all.data());
+    for (int s = 0; s < n; ++s) {
+        if (steps) steps[s] = taken[s];
+        if (r) r[s] = res[s];
+    }
+    return st;
+}
+
+rlbm_status rlbm_batch_autotune(rlbm_batch *B, int trial_steps, double *ms_per_step)
+{
+    if (!B || trial_steps < 1) return fail(RLBM_EINVAL, "rlbm_batch_autotune: bad argument");
+    const int n = (int)B->lat.size();
+    // save every sample's state on the device: current populations, fields, previous velocities
+    std::vector<size_t> off(n + 1, 0);
+    for (int s = 0; s < n; ++s) {
+        const rlbm_lattice *L = B->lat[s];
+        off[s + 1] = off[s] + (size_t)L->plane() * (kQ * store_bytes(L->storage) + 6 * sizeof(double));
+    }
+    char *save = nullptr;
+    HIP_TRY(hipMalloc((void **)&save, off[n]));
+    std::vector<int> cur0(n);
+    std::vector<int64_t> t0(n), k0(n);
+    for (int s = 0; s < n; ++s) {
+        rlbm_lattice *L = B->lat[s];
+        const size_t P = (size_t)L->plane(), pb = P * kQ * store_bytes(L->storage);
+        cur0[s] = L->cur;
+        t0[s] = L->t;
+        k0[s] = L->last_K;
+        HIP_TRY(hipMemcpyAsync(save + off[s], L->pop[L->cur], pb, hipMemcpyDeviceToDevice, B->stream));
+        HIP_TRY(hipMemcpyAsync(save + off[s] + pb, L->fld, 4 * P * 8, hipMemcpyDeviceToDevice, B->stream));
+        HIP_TRY(hipMemcpyAsync(save + off[s] + pb + 4 * P * 8, L->prev, 2 * P * 8, hipMemcpyDeviceToDevice, B->stream));
+    }
+    std::vector<LaunchShape> shape0(n);
+    for (int s = 0; s < n; ++s) shape0[s] = B->lat[s]->shape;
+    const int tiles[3] = {64, 128, 256};
+    double best = INFINITY;
+    int best_c = -1;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    rlbm_status st = RLBM_OK;
+    for (int c = 0; c < 3 && st == RLBM_OK; ++c) {
+        for (int s = 0; s < n; ++s) {
+            const int w = B->lat[s]->nx - 2 * kReach;
+            int t = tiles[c];
+            while (t > 64 && t / 2 >= w) t /= 2;
+            B->lat[s]->shape = LaunchShape{t, 256 / t};
+        }
+        st = rlbm_batch_step(B, 2, 0);
+        if (st) break;
+        (void)hipEventRecord(e0, B->stream);
+        st = rlbm_batch_step(B, trial_steps, 0);
+        if (st) break;
+        (void)hipEventRecord(e1, B->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double per = ms / trial_steps;
+        if (ms_per_step) ms_per_step[c] = per;
+        if (per < best) {
+            best = per;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int s = 0; s < n; ++s) {
+        rlbm_lattice *L = B->lat[s];
+        const size_t P = (size_t)L->plane(), pb = P * kQ * store_bytes(L->storage);
+        L->cur = cur0[s];
+        L->t = t0[s];
+        L->last_K = k0[s];
+        hipError_t e = hipMemcpyAsync(L->pop[L->cur], save + off[s], pb, hipMemcpyDeviceToDevice, B->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(L->fld, save + off[s] + pb, 4 * P * 8, hipMemcpyDeviceToDevice, B->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(L->prev, save + off[s] + pb + 4 * P * 8, 2 * P * 8, hipMemcpyDeviceToDevice, B->stream);
+        if (e != hipSuccess && !st) st = fail(RLBM_EDEVICE, "rlbm_batch_autotune: restore: %s", hipGetErrorString(e));
+        if (best_c >= 0) {
+            const int w = L->nx - 2 * kReach;
+            int t = tiles[best_c];
+            while (t > 64 && t / 2 >= w) t /= 2;
+            L->shape = LaunchShape{t, 256 / t};
+        } else {
+            L->shape = shape0[s];
+        }
+    }
+    {
+        hipError_t e = hipStreamSynchronize(B->stream);
+        if (e != hipSuccess && !st) st = fail(RLBM_EDEVICE, "rlbm_batch_autotune: %s", hipGetErrorString(e));
+    }
+    dfree(save);
+    if (B->exec) {
+        (void)hipGraphExecDestroy(B->exec);
+        B->exec = nullptr;
+        (void)hipGraphDestroy(B->graph);
+        B->graph = nullptr;
+    }
+    return st;
 }
 
 }  // extern "C"

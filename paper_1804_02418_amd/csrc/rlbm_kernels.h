@@ -135,6 +135,21 @@ struct StepArgs {
 
 enum class Store { F64 = 0, F32 = 1, F16 = 2 };
 
+// One sample of a batch: its step arguments (fields pointers included), its
+// two population buffers and its step-grid geometry.  The buffer holding the
+// current state is pop[parity ^ parity_xor] for the batch-wide step parity.
+template <class R>
+struct BatchDesc {
+    StepArgs<R> a;
+    void *pop[2];
+    const double *pvx, *pvy;  // velocities at the end of the previous batch step call
+    int nbnd, tile_x, tiles_x, all;
+    int parity_xor, pad_;
+};
+
+// Work item = (sample << kItemBlockBits) | block of that sample's step grid.
+constexpr int kItemBlockBits = 20;
+
 struct LaunchShape {
     int tile_x;  // sites per block along x (multiple of 64)
     int rows;    // rows per block
@@ -144,6 +159,15 @@ struct LaunchShape {
 // interior kernel for the sites whose whole stencil lies on the lattice
 // (none when there is a mask) and a boundary kernel for the rest.
 hipError_t launch_step(Store st, const void *args, const void *src, void *dst, LaunchShape shape, hipStream_t s);
+
+// Batched step: `grid` persistent blocks drain *n_items work items.
+hipError_t launch_batch_step(Store st, const void *descs, const unsigned *items, const int *n_items,
+                             unsigned *counters, int grid, int parity, int write_fields, hipStream_t s);
+// Blocks of the batched step kernel that fit on the device at once.
+int batch_resident_blocks(Store st);
+// Per-sample residual partial sums (3 doubles per block, blocks_per_sample per sample).
+hipError_t launch_batch_residual(Store st, const void *descs, int nsamples, int blocks_per_sample, double *part,
+                                 hipStream_t s);
 
 // Initial post-collision state from fields (n, T, vx, vy; null pointers ->
 // the uniform values u[4]).  Writes dst and the fields of the initial state.

@@ -213,16 +213,16 @@ __device__ __forceinline__ void gather_general(const StepArgs<R> &A, const S *__
     }
 }
 
-// One time step.  A 1-D grid of 256-thread blocks: the first nbnd blocks
-// take the boundary sites (general gather), the rest tile the interior
-// x in [5, nx - 5), y in [5, ny - 5) with tile_x * rows sites per block,
-// tiles aligned to tile_x so every wavefront stores 64 aligned values.
-// Boundary blocks come first so that they run alongside interior tiles.
+// One block of a time step.  The step's 1-D grid of 256-thread blocks: the
+// first nbnd blocks take the boundary sites (gather table or computed
+// gather), the rest tile the interior x in [5, nx - 5), y in [5, ny - 5)
+// with tile_x * rows sites per block, tiles aligned to tile_x so every
+// wavefront stores 64 aligned values.
 template <class S, class R>
-__global__ __launch_bounds__(256) void step_kernel(const StepArgs<R> A, const S *__restrict__ src,
-                                                   S *__restrict__ dst, int nbnd, int tile_x, int tiles_x, int all)
+__device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__restrict__ src, S *__restrict__ dst,
+                                           int b, int nbnd, int tile_x, int tiles_x, int all, int wf)
 {
-    const int b = blockIdx.x, t = threadIdx.x;
+    const int t = threadIdx.x;
     const int nx = A.nx;
     const long long P = A.plane;
     int x, y;
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs<R> A, const S 
         boundary_site(idx, nx, A.ny, all, x, y);
         const long long site = (long long)y * nx + x;
         if (A.has_mask && A.mask[site]) {
-            if (A.write_fields) {
+            if (wf) {
                 A.fn[site] = 0.0;
                 A.fvx[site] = 0.0;
                 A.fvy[site] = 0.0;
@@ -272,11 +272,100 @@ __global__ __launch_bounds__(256) void step_kernel(const StepArgs<R> A, const S 
     const unsigned site = (unsigned)y * (unsigned)nx + (unsigned)x;
     SiteFields f;
     const bool ok = collide_site<R>(h, A, f);
-    if (A.write_fields) write_fields(A, site, f, ok);
+    if (wf) write_fields(A, site, f, ok);
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         S *__restrict__ plane = dst + (long long)i * P;
         StoreIO<S>::template store<R>(plane + site, h[i]);
+    }
+}
+
+template <class S, class R>
+__global__ __launch_bounds__(256) void step_kernel(const StepArgs<R> A, const S *__restrict__ src,
+                                                   S *__restrict__ dst, int nbnd, int tile_x, int tiles_x, int all)
+{
+    step_block<S, R>(A, src, dst, blockIdx.x, nbnd, tile_x, tiles_x, all, A.write_fields);
+}
+
+// Batched step: a persistent grid drains the work list of (sample, block)
+// items through an atomic counter; each item is one block of that sample's
+// step grid.  The last block to leave resets the counters, so the next launch
+// (or graph replay) starts from zero without a memset.
+template <class S, class R>
+__global__ __launch_bounds__(256) void batch_step_kernel(const BatchDesc<R> *__restrict__ descs,
+                                                         const unsigned *__restrict__ items,
+                                                         const int *__restrict__ n_items_p,
+                                                         unsigned *__restrict__ counters, int parity, int wf)
+{
+    __shared__ unsigned s_item;
+    const unsigned n_items = (unsigned)*n_items_p;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&counters[0], 1u);
+        __syncthreads();
+        const unsigned k = s_item;
+        __syncthreads();
+        if (k >= n_items) break;
+        const unsigned it = __builtin_amdgcn_readfirstlane(items[k]);
+        const int smp = (int)(it >> kItemBlockBits), b = (int)(it & ((1u << kItemBlockBits) - 1));
+        const BatchDesc<R> &D = descs[smp];
+        const int par = parity ^ D.parity_xor;
+        step_block<S, R>(D.a, static_cast<const S *>(D.pop[par]), static_cast<S *>(D.pop[par ^ 1]), b, D.nbnd, D.tile_x,
+                         D.tiles_x, D.all, wf);
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned done = atomicAdd(&counters[1], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&counters[0], 0u);
+            atomicExch(&counters[1], 0u);
+        }
+    }
+}
+
+// Per-sample residual partial sums: block (s, j) covers sites j, j + B*256,
+// ... of sample s; part[(s * B + j) * 3 + {0,1,2}] = |u - u_prev|^2, |u|^2,
+// unhealthy count.
+template <class R>
+__global__ __launch_bounds__(256) void batch_residual_kernel(const BatchDesc<R> *__restrict__ descs,
+                                                             double *__restrict__ part)
+{
+    const int smp = blockIdx.y, B = gridDim.x;
+    const BatchDesc<R> &D = descs[smp];
+    const long long n = D.a.plane;
+    double dv = 0.0, vv = 0.0, bad = 0.0;
+    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += (long long)B * blockDim.x) {
+        if (D.a.has_mask && D.a.mask[s]) continue;
+        const double a = D.a.fvx[s], b = D.a.fvy[s], dn = D.a.fn[s];
+        const double ex = a - D.pvx[s], ey = b - D.pvy[s];
+        const double v2 = a * a + b * b;
+        if (!(dn > 0.0) || !(v2 < 1.0) || !isfinite(a) || !isfinite(b) || !isfinite(dn)) bad += 1.0;
+        dv += ex * ex + ey * ey;
+        vv += v2;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        dv += __shfl_down(dv, off, 64);
+        vv += __shfl_down(vv, off, 64);
+        bad += __shfl_down(bad, off, 64);
+    }
+    __shared__ double red[3][256 / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wid] = dv;
+        red[1][wid] = vv;
+        red[2][wid] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0, s1 = 0, s2 = 0;
+        for (int w = 0; w < (int)(blockDim.x / 64); ++w) {
+            s0 += red[0][w];
+            s1 += red[1][w];
+            s2 += red[2][w];
+        }
+        double *o = part + ((long long)smp * B + blockIdx.x) * 3;
+        o[0] = s0;
+        o[1] = s1;
+        o[2] = s2;
     }
 }
 
@@ -410,7 +499,61 @@ hipError_t launch_init_t(const void *args, const double *n, const double *T, con
     return hipGetLastError();
 }
 
+template <class S, class R>
+hipError_t launch_batch_t(const void *descs, const unsigned *items, const int *n_items, unsigned *counters, int grid,
+                          int parity, int wf, hipStream_t s)
+{
+    hipLaunchKernelGGL((batch_step_kernel<S, R>), dim3(grid), dim3(256), 0, s,
+                       static_cast<const BatchDesc<R> *>(descs), items, n_items, counters, parity, wf);
+    return hipGetLastError();
+}
+
+template <class S, class R>
+int batch_grid_t()
+{
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<S, R>, 256, 0) != hipSuccess) return 0;
+    return per_cu * prop.multiProcessorCount;
+}
+
 }  // namespace
+
+hipError_t launch_batch_step(Store st, const void *descs, const unsigned *items, const int *n_items,
+                             unsigned *counters, int grid, int parity, int write_fields, hipStream_t s)
+{
+    switch (st) {
+    case Store::F64: return launch_batch_t<double, double>(descs, items, n_items, counters, grid, parity, write_fields, s);
+    case Store::F32: return launch_batch_t<float, float>(descs, items, n_items, counters, grid, parity, write_fields, s);
+    case Store::F16:
+        return launch_batch_t<_Float16, float>(descs, items, n_items, counters, grid, parity, write_fields, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+int batch_resident_blocks(Store st)
+{
+    switch (st) {
+    case Store::F64: return batch_grid_t<double, double>();
+    case Store::F32: return batch_grid_t<float, float>();
+    case Store::F16: return batch_grid_t<_Float16, float>();
+    }
+    return 0;
+}
+
+hipError_t launch_batch_residual(Store st, const void *descs, int nsamples, int blocks_per_sample, double *part,
+                                 hipStream_t s)
+{
+    const dim3 grid(blocks_per_sample, nsamples);
+    if (st == Store::F64)
+        hipLaunchKernelGGL(batch_residual_kernel<double>, grid, dim3(256), 0, s,
+                           static_cast<const BatchDesc<double> *>(descs), part);
+    else
+        hipLaunchKernelGGL(batch_residual_kernel<float>, grid, dim3(256), 0, s,
+                           static_cast<const BatchDesc<float> *>(descs), part);
+    return hipGetLastError();
+}
 
 hipError_t launch_step(Store st, const void *args, const void *src, void *dst, LaunchShape shape, hipStream_t s)
 {

@@ -1,0 +1,111 @@
+"""GPU tests of the batched persistent launch.
+
+Every sample of a batch must evolve bit-identically to the same lattice
+stepped alone (the step of a site is a pure function of the previous state,
+whatever block or launch computes it), through eager launches and through
+graph replays; frozen samples must not change; the batched residual must
+equal the single-lattice residual; the batch autotuner must leave every
+state as it found it.
+"""
+import numpy as np
+import pytest
+
+from harness import gpu_lattice
+from paper_1804_02418_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _samples():
+    out = []
+    for k, (nx, ny) in enumerate([(64, 48), (200, 90), (128, 128), (75, 31), (320, 64), (9, 40)]):
+        w = workloads.small_device(nx=nx, ny=ny, steps=1)
+        w["contacts"] = w["contacts"][:3]
+        w["tau"] = 0.6 + 0.15 * k
+        w["F"] = (1e-4 * (k + 1), -2e-5 * k)
+        w["init"] = dict(n=1.0 + 0.01 * k, T=1.0 - 0.01 * k, vx=0.001 * k, vy=0.0)
+        if k == 2:
+            w.update(periodic_x=True, periodic_y=True, contacts=[])
+        if k == 5:
+            w.update(periodic_x=True, contacts=[c for c in w["contacts"] if c["edge"] != "left"])
+        out.append(w)
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_matches_single_lattices(storage, graph):
+    import paper_1804_02418_amd as rl
+
+    ws = _samples()
+    B = rl.Batch(ws, storage)
+    singles = [gpu_lattice(w, storage) for w in ws]
+    for n in (1, 70):
+        B.step(n, graph=graph)
+        for L in singles:
+            L.step(n)
+    for k, (L, bl) in enumerate(zip(singles, B.lattices)):
+        assert bl.time == L.time == 71
+        assert np.array_equal(bl.read_populations(), L.read_populations()), k
+        fa, fb = bl.read_fields(), L.read_fields()
+        for key in fa:
+            assert np.array_equal(fa[key], fb[key]), (k, key)
+    r = B.residual()
+    for k, L in enumerate(singles):
+        assert r[k] == pytest.approx(L.residual(), rel=1e-12, abs=0)
+    print(storage, "graph" if graph else "eager", "sites", B.sites(), "residuals", r, flush=True)
+    B.close()
+
+
+def test_frozen_samples_keep_their_state():
+    import paper_1804_02418_amd as rl
+
+    ws = _samples()
+    B = rl.Batch(ws, "f64")
+    B.step(5)
+    before = [bl.read_populations() for bl in B.lattices]
+    active = np.ones(len(ws), dtype=np.uint8)
+    active[[1, 4]] = 0
+    B.set_active(active)
+    B.step(40)
+    for k, bl in enumerate(B.lattices):
+        if active[k]:
+            assert bl.time == 45 and not np.array_equal(bl.read_populations(), before[k])
+        else:
+            assert bl.time == 5 and np.array_equal(bl.read_populations(), before[k])
+    # reactivated samples continue exactly as if never frozen
+    B.set_active(np.ones(len(ws), dtype=np.uint8))
+    B.step(3)
+    ref = gpu_lattice(ws[1], "f64")
+    ref.step(8)
+    assert np.array_equal(B.lattices[1].read_populations(), ref.read_populations())
+
+
+def test_batch_autotune_restores_state():
+    import paper_1804_02418_amd as rl
+
+    ws = _samples()
+    B = rl.Batch(ws, "f32")
+    B.step(4)
+    snap = [bl.read_populations() for bl in B.lattices]
+    ms = B.autotune(3)
+    print("batch autotune ms/step", ms, flush=True)
+    assert (ms > 0).all()
+    for k, bl in enumerate(B.lattices):
+        assert bl.time == 4 and np.array_equal(bl.read_populations(), snap[k])
+    B.step(6)
+    single = gpu_lattice(ws[3], "f32")
+    single.step(10)
+    assert np.array_equal(B.lattices[3].read_populations(), single.read_populations())
+
+
+def test_batch_step_until_freezes_converged_samples():
+    import paper_1804_02418_amd as rl
+
+    ws = _samples()[:3]
+    B = rl.Batch(ws, "f64")
+    steps, r = B.step_until(400, 50, 1e-3)
+    print("step_until steps", steps, "r", r, flush=True)
+    assert ((r < 1e-3) | (steps == 400)).all()
+    for k, bl in enumerate(B.lattices):
+        assert bl.time == steps[k]
