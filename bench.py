@@ -65,13 +65,17 @@ def make_lattice(w, storage, stream):
     return L
 
 
-def run_gpu(w, storage, steps, warmup):
-    """Returns (seconds for `steps` steps, average launch ms) timed with HIP
-    events on the lattice's stream (torch's current stream)."""
+def run_gpu(w, storage, steps, warmup, autotune=True):
+    """Returns (seconds for `steps` steps, average launch ms, residual)
+    timed with HIP events on the lattice's stream (torch's current stream).
+    The library's autotuner picks the launch shape first (its trials are
+    rolled back, so the timed steps start from the same state)."""
     import torch
 
     stream = torch.cuda.current_stream()
     L = make_lattice(w, storage, stream.cuda_stream)
+    if autotune:
+        L.autotune(10)
     L.step(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -143,6 +147,7 @@ def main(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps for the CPU baseline (0 = skip)")
     ap.add_argument("--variants", action="store_true", help="also time the other storages and 4096x2048")
     ap.add_argument("--copy-bytes", type=int, default=0, help="only run the copy-bandwidth calibration")
+    ap.add_argument("--no-autotune", action="store_true", help="time the default launch shape")
     args = ap.parse_args(argv)
 
     if args.copy_bytes:
@@ -158,7 +163,7 @@ def main(argv=None):
 
     w = workloads.graphene_sample(args.nx, args.ny, storage=args.storage, steps=args.steps)
     sites = w["nx"] * w["ny"]
-    secs, launch_ms, resid = run_gpu(w, args.storage, args.steps, args.warmup)
+    secs, launch_ms, resid = run_gpu(w, args.storage, args.steps, args.warmup, not args.no_autotune)
     mlups = sites * args.steps / secs / 1e6
     bytes_per_launch = 2 * 48 * BYTES_PER_POP[args.storage] * sites
     achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9

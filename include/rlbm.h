@@ -192,15 +192,24 @@ rlbm_status rlbm_set_state(rlbm_lattice *lat, const void *src, size_t bytes);
  * to 64. */
 rlbm_status rlbm_set_launch_shape(rlbm_lattice *lat, int tile_x, int rows);
 
+/* Streaming (non-temporal) stores of the populations: on = 1 makes the step
+ * kernel's stores bypass the caches.  Pays off once the two population
+ * arrays outgrow the 256 MB Infinity Cache (the default there); below it the
+ * next step's reads hit the cache and ordinary stores are faster.  Results
+ * are identical either way. */
+rlbm_status rlbm_set_streaming_stores(rlbm_lattice *lat, int on);
+
 /* Autotuner: time every candidate launch shape of the step kernel on this
- * lattice (trial_steps timed steps each, after 2 warm-up steps, with HIP
+ * lattice -- tile_x 64, 128, 256, each with ordinary and with streaming
+ * stores -- (trial_steps timed steps each, after 2 warm-up steps, with HIP
  * events on the lattice's stream), keep the fastest, and remember it for
  * lattices of the same device architecture, storage, size and mask use in
  * this process (and in the text file named by the environment variable
  * RLBM_TUNE_CACHE, if set, which later processes read at rlbm_create).  The
  * lattice state, time and fields are restored afterwards.  ms_per_step
- * (optional, 3 entries, caller-owned) receives the timings of tile_x = 64,
- * 128, 256 (0 for a shape that does not apply).  Synchronises. */
+ * (optional, 6 entries, caller-owned) receives the timings of tile_x = 64,
+ * 128, 256 with ordinary stores, then the same with streaming stores (0 for
+ * a shape that does not apply).  Synchronises. */
 rlbm_status rlbm_autotune(rlbm_lattice *lat, int trial_steps, double *ms_per_step);
 
 /* Block until all work queued on the lattice's stream is done. */
@@ -259,8 +268,8 @@ rlbm_status rlbm_batch_step_until(rlbm_batch *b, int64_t max_steps, int64_t chec
 
 /* Autotuner for the batch: time the batched step with every sample's tile
  * width set to each candidate (64, 128, 256, capped at the sample's interior
- * width), keep the fastest, restore all states.  ms_per_step: 3 entries or
- * NULL. */
+ * width), with ordinary and with streaming stores, keep the fastest, restore
+ * all states.  ms_per_step: 6 entries or NULL. */
 rlbm_status rlbm_batch_autotune(rlbm_batch *b, int trial_steps, double *ms_per_step);
 
 /* Total lattice sites of the active samples. */

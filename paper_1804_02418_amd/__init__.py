@@ -6,8 +6,8 @@ of ``include/rlbm.h``; this package only marshals arguments to it.  Importing
 ``Lattice`` or calling any function loads the library and raises if it has
 not been built: there is no CPU fallback.
 """
-from ._binding import (EDGE, F16DEV, F32, F64, Batch, Lattice, RlbmError, Unstable, check, force_matrices, lib,
-                       quadrature)
+from ._binding import (EDGE, F16DEV, F32, F64, Batch, Lattice, RlbmError, UNet, Unstable, check, conv3x3_backward_data,
+                       conv3x3_backward_weight, conv3x3_forward, force_matrices, lib, quadrature)
 
-__all__ = ["Lattice", "Batch", "RlbmError", "Unstable", "quadrature", "force_matrices", "lib", "check",
+__all__ = ["Lattice", "Batch", "UNet", "conv3x3_forward", "conv3x3_backward_data", "conv3x3_backward_weight", "RlbmError", "Unstable", "quadrature", "force_matrices", "lib", "check",
            "F64", "F32", "F16DEV", "EDGE"]

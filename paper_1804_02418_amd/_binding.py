@@ -77,6 +77,7 @@ SIGNATURES = {
     "rlbm_set_state": ([_vp, _vp, ctypes.c_size_t], None),
     "rlbm_set_launch_shape": ([_vp, ctypes.c_int, ctypes.c_int], None),
     "rlbm_autotune": ([_vp, ctypes.c_int, _dp], None),
+    "rlbm_set_streaming_stores": ([_vp, ctypes.c_int], None),
     "rlbm_synchronize": ([_vp], None),
     "rlbm_batch_create": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)], None),
     "rlbm_batch_destroy": ([_vp], "void"),
@@ -87,6 +88,25 @@ SIGNATURES = {
     "rlbm_batch_step_until": ([_vp, _i64, _i64, ctypes.c_double, _vp, _dp], None),
     "rlbm_batch_autotune": ([_vp, ctypes.c_int, _dp], None),
     "rlbm_batch_sites": ([_vp, ctypes.POINTER(_i64)], None),
+    # surrogate (include/rlbm_surrogate.h)
+    "rlbm_unet_create": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_uint64, _vp, ctypes.POINTER(_vp)], None),
+    "rlbm_unet_destroy": ([_vp], "void"),
+    "rlbm_unet_param_count": ([_vp, ctypes.POINTER(_i64)], None),
+    "rlbm_unet_set_params": ([_vp, _vp], None),
+    "rlbm_unet_get_params": ([_vp, _vp], None),
+    "rlbm_unet_get_grads": ([_vp, _vp], None),
+    "rlbm_unet_forward": ([_vp, _vp, _vp, ctypes.c_int], None),
+    "rlbm_unet_mse": ([_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_float), _vp], None),
+    "rlbm_unet_backward": ([_vp, _vp, ctypes.c_int, _vp], None),
+    "rlbm_unet_zero_grad": ([_vp], None),
+    "rlbm_unet_adam_step": ([_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float], None),
+    "rlbm_conv3x3_forward": ([_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.c_int, ctypes.c_int, _vp], None),
+    "rlbm_conv3x3_backward_data": ([_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int, _vp], None),
+    "rlbm_conv3x3_backward_weight": ([_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int, _vp], None),
 }
 
 
@@ -94,6 +114,12 @@ def lib() -> ctypes.CDLL:
     """Load the in-tree librlbm.so; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname as the system
+        # one; load it first so that torch and librlbm share one runtime.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_1804_02418_amd.build.build() "
                               "(there is no CPU fallback)")
@@ -249,9 +275,13 @@ class Lattice:
     def set_launch_shape(self, tile_x: int, rows: int):
         check(lib().rlbm_set_launch_shape(self._h, int(tile_x), int(rows)))
 
+    def set_streaming_stores(self, on: bool):
+        check(lib().rlbm_set_streaming_stores(self._h, int(bool(on))))
+
     def autotune(self, trial_steps: int = 20):
-        """Pick the fastest launch shape; returns ms/step for tile_x 64, 128, 256."""
-        ms = np.zeros(3)
+        """Pick the fastest launch shape; returns ms/step for tile_x 64, 128,
+        256 with ordinary stores, then with streaming stores."""
+        ms = np.zeros(6)
         check(lib().rlbm_autotune(self._h, int(trial_steps), ms.ctypes.data_as(_dp)))
         return ms
 
@@ -335,7 +365,7 @@ class Batch:
         return steps, r
 
     def autotune(self, trial_steps: int = 10) -> np.ndarray:
-        ms = np.zeros(3)
+        ms = np.zeros(6)
         check(lib().rlbm_batch_autotune(self._h, int(trial_steps), ms.ctypes.data_as(_dp)))
         return ms
 
@@ -343,3 +373,93 @@ class Batch:
         n = _i64()
         check(lib().rlbm_batch_sites(self._h, ctypes.byref(n)))
         return n.value
+
+
+def _ptr(t):
+    """Device pointer of a contiguous torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    assert t.is_contiguous()
+    return t.data_ptr()
+
+
+def _stream_ptr(stream):
+    return None if stream is None else _vp(stream)
+
+
+class UNet:
+    """The warm-start surrogate network (include/rlbm_surrogate.h).  Inputs
+    and outputs are device float32 torch tensors in NHWC layout."""
+
+    def __init__(self, base=16, cin=16, cout=3, height=256, width=256, max_batch=8, seed=1, stream=None):
+        h = _vp()
+        check(lib().rlbm_unet_create(int(base), int(cin), int(cout), int(height), int(width), int(max_batch),
+                                     int(seed), _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+        self.base, self.cin, self.cout, self.height, self.width, self.max_batch = base, cin, cout, height, width, max_batch
+        n = _i64()
+        check(lib().rlbm_unet_param_count(self._h, ctypes.byref(n)))
+        self.nparam = n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rlbm_unet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.size == self.nparam
+        check(lib().rlbm_unet_set_params(self._h, a.ctypes.data))
+
+    def get_params(self) -> np.ndarray:
+        a = np.empty(self.nparam, dtype=np.float32)
+        check(lib().rlbm_unet_get_params(self._h, a.ctypes.data))
+        return a
+
+    def get_grads(self) -> np.ndarray:
+        a = np.empty(self.nparam, dtype=np.float32)
+        check(lib().rlbm_unet_get_grads(self._h, a.ctypes.data))
+        return a
+
+    def forward(self, x, y):
+        check(lib().rlbm_unet_forward(self._h, _ptr(x), _ptr(y), int(x.shape[0])))
+
+    def mse(self, y, t, dy=None) -> float:
+        loss = ctypes.c_float()
+        check(lib().rlbm_unet_mse(self._h, _ptr(y), _ptr(t), int(y.shape[0]), ctypes.byref(loss), _ptr(dy)))
+        return loss.value
+
+    def backward(self, dy, dx=None):
+        check(lib().rlbm_unet_backward(self._h, _ptr(dy), int(dy.shape[0]), _ptr(dx)))
+
+    def zero_grad(self):
+        check(lib().rlbm_unet_zero_grad(self._h))
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        check(lib().rlbm_unet_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps)))
+
+
+def conv3x3_forward(x, w, b, y, relu=True, stream=None):
+    B, H, W, ci = x.shape
+    co = w.shape[0]
+    check(lib().rlbm_conv3x3_forward(_ptr(x), _ptr(w), _ptr(b), _ptr(y), B, H, W, ci, co, int(bool(relu)),
+                                     _stream_ptr(stream)))
+
+
+def conv3x3_backward_data(dy, w, dx, stream=None):
+    B, H, W, co = dy.shape
+    ci = w.shape[3]
+    check(lib().rlbm_conv3x3_backward_data(_ptr(dy), _ptr(w), _ptr(dx), B, H, W, ci, co, _stream_ptr(stream)))
+
+
+def conv3x3_backward_weight(dy, x, gw, gb=None, stream=None):
+    B, H, W, co = dy.shape
+    ci = x.shape[3]
+    check(lib().rlbm_conv3x3_backward_weight(_ptr(dy), _ptr(x), _ptr(gw), _ptr(gb), B, H, W, ci, co,
+                                             _stream_ptr(stream)))

@@ -27,6 +27,19 @@ thread_local std::string g_error;
 // release paths ignore HIP errors on purpose (nothing useful can be done)
 inline void dfree(void *p) { (void)hipFree(p); }
 
+}  // namespace
+
+namespace rlbm {
+// Error reporting shared by the other translation units of the library.
+rlbm_status set_error(rlbm_status st, const char *msg)
+{
+    g_error = msg ? msg : "";
+    return st;
+}
+}  // namespace rlbm
+
+namespace {
+
 rlbm_status fail(rlbm_status st, const char *fmt, ...)
 {
     char buf[512];
@@ -109,6 +122,7 @@ struct rlbm_lattice {
     int64_t last_K = 0;
     int cur = 0;
     LaunchShape shape{256, 1};
+    int nt_store = 0;  // streaming (non-temporal) population stores
     // device buffers
     void *pop[2] = {nullptr, nullptr};
     double *fld = nullptr;   // 4 planes: n, vx, vy, eps
@@ -143,6 +157,7 @@ void fill_args(rlbm_lattice *L, StepArgs<R> &A)
     A.has_mask = L->mask != nullptr;
     A.has_force = (L->Fx != 0.0 || L->Fy != 0.0);
     A.write_fields = 0;
+    A.nt_store = L->nt_store;
     A.plane = L->plane();
     for (int j = 0; j < kShells; ++j) {
         A.wp0[0][j] = R(L->scale * q.w1[j] * q.p0[j]);
@@ -401,11 +416,16 @@ rlbm_status rlbm_create(int nx, int ny, rlbm_storage storage, void *hip_stream, 
     L->stream = static_cast<hipStream_t>(hip_stream);
     L->scale = storage == RLBM_F16DEV ? 1.0 / 4096.0 : 1.0;
     L->shape = default_shape(nx);
+    // populations that outgrow the 256 MB Infinity Cache are streamed
+    L->nt_store = 2.0 * (double)nx * ny * kQ * store_bytes(storage) > 256.0 * 1024 * 1024 ? 1 : 0;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_cache_load();
         auto it = g_tune.find(TuneKey(device_arch(), (int)storage, nx, ny, 0));
-        if (it != g_tune.end()) L->shape = LaunchShape{it->second, 256 / it->second};
+        if (it != g_tune.end()) {
+            L->shape = LaunchShape{it->second / 2, 256 / (it->second / 2)};
+            L->nt_store = it->second & 1;
+        }
     }
     const size_t P = (size_t)nx * ny;
     const size_t pop_bytes = P * kQ * store_bytes(storage);
@@ -794,12 +814,15 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
     if (e == hipSuccess) e = hipEventCreate(&e1);
     const int tiles[3] = {64, 128, 256};
     double best = INFINITY;
-    int best_tile = shape0.tile_x;
+    int best_tile = shape0.tile_x, best_nt = L->nt_store;
+    const int nt0 = L->nt_store;
     const int interior_w = L->nx - 2 * kReach;
-    for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+    for (int c = 0; c < 6 && e == hipSuccess; ++c) {
+        const int tc = c % 3, nt = c / 3;
         if (ms_per_step) ms_per_step[c] = 0.0;
-        if (c > 0 && tiles[c - 1] >= interior_w) continue;  // wider tiles only add idle lanes
-        L->shape = LaunchShape{tiles[c], 256 / tiles[c]};
+        if (tc > 0 && tiles[tc - 1] >= interior_w) continue;  // wider tiles only add idle lanes
+        L->shape = LaunchShape{tiles[tc], 256 / tiles[tc]};
+        rlbm_set_streaming_stores(L, nt);
         rlbm_status st = rlbm_step(L, 2);
         if (st == RLBM_OK) e = hipEventRecord(e0, L->stream);
         if (st == RLBM_OK && e == hipSuccess) st = rlbm_step(L, trial_steps);
@@ -815,7 +838,8 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
         if (ms_per_step) ms_per_step[c] = per;
         if (per < best) {
             best = per;
-            best_tile = tiles[c];
+            best_tile = tiles[tc];
+            best_nt = nt;
         }
     }
     // restore
@@ -834,11 +858,22 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
     L->fields_valid = fv0;
     if (e != hipSuccess) {
         L->shape = shape0;
+        rlbm_set_streaming_stores(L, nt0);
         return fail(RLBM_EDEVICE, "rlbm_autotune: %s", hipGetErrorString(e));
     }
     L->shape = LaunchShape{best_tile, 256 / best_tile};
+    rlbm_set_streaming_stores(L, best_nt);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    tune_cache_store(TuneKey(device_arch(), (int)L->storage, L->nx, L->ny, L->mask ? 1 : 0), best_tile);
+    tune_cache_store(TuneKey(device_arch(), (int)L->storage, L->nx, L->ny, L->mask ? 1 : 0), 2 * best_tile + best_nt);
+    return RLBM_OK;
+}
+
+rlbm_status rlbm_set_streaming_stores(rlbm_lattice *L, int on)
+{
+    CHECK_L(L);
+    L->nt_store = on ? 1 : 0;
+    L->args_d.nt_store = L->nt_store;
+    L->args_f.nt_store = L->nt_store;
     return RLBM_OK;
 }
 
@@ -1208,12 +1243,15 @@ rlbm_status rlbm_batch_autotune(rlbm_batch *B, int trial_steps, double *ms_per_s
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     rlbm_status st = RLBM_OK;
-    for (int c = 0; c < 3 && st == RLBM_OK; ++c) {
+    std::vector<int> nt0(n);
+    for (int s = 0; s < n; ++s) nt0[s] = B->lat[s]->nt_store;
+    for (int c = 0; c < 6 && st == RLBM_OK; ++c) {
         for (int s = 0; s < n; ++s) {
             const int w = B->lat[s]->nx - 2 * kReach;
-            int t = tiles[c];
+            int t = tiles[c % 3];
             while (t > 64 && t / 2 >= w) t /= 2;
             B->lat[s]->shape = LaunchShape{t, 256 / t};
+            rlbm_set_streaming_stores(B->lat[s], c / 3);
         }
         st = rlbm_batch_step(B, 2, 0);
         if (st) break;
@@ -1246,11 +1284,13 @@ rlbm_status rlbm_batch_autotune(rlbm_batch *B, int trial_steps, double *ms_per_s
         if (e != hipSuccess && !st) st = fail(RLBM_EDEVICE, "rlbm_batch_autotune: restore: %s", hipGetErrorString(e));
         if (best_c >= 0) {
             const int w = L->nx - 2 * kReach;
-            int t = tiles[best_c];
+            int t = tiles[best_c % 3];
             while (t > 64 && t / 2 >= w) t /= 2;
             L->shape = LaunchShape{t, 256 / t};
+            rlbm_set_streaming_stores(L, best_c / 3);
         } else {
             L->shape = shape0[s];
+            rlbm_set_streaming_stores(L, nt0[s]);
         }
     }
     {

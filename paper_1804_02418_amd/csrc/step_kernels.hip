@@ -25,6 +25,8 @@ struct StoreIO<double> {
     __device__ static R load(const double *p) { return R(*p); }
     template <class R>
     __device__ static void store(double *p, R v) { *p = double(v); }
+    template <class R>
+    __device__ static void store_nt(double *p, R v) { __builtin_nontemporal_store(double(v), p); }
 };
 template <>
 struct StoreIO<float> {
@@ -32,6 +34,8 @@ struct StoreIO<float> {
     __device__ static R load(const float *p) { return R(*p); }
     template <class R>
     __device__ static void store(float *p, R v) { *p = float(v); }
+    template <class R>
+    __device__ static void store_nt(float *p, R v) { __builtin_nontemporal_store(float(v), p); }
 };
 template <>
 struct StoreIO<_Float16> {
@@ -39,6 +43,8 @@ struct StoreIO<_Float16> {
     __device__ static R load(const _Float16 *p) { return R(float(*p)); }
     template <class R>
     __device__ static void store(_Float16 *p, R v) { *p = _Float16(float(v)); }
+    template <class R>
+    __device__ static void store_nt(_Float16 *p, R v) { __builtin_nontemporal_store(_Float16(float(v)), p); }
 };
 
 struct SiteFields {
@@ -273,10 +279,16 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
     SiteFields f;
     const bool ok = collide_site<R>(h, A, f);
     if (wf) write_fields(A, site, f, ok);
+    if (A.nt_store) {
+        // streaming stores: the next step reads these values once, from HBM
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        S *__restrict__ plane = dst + (long long)i * P;
-        StoreIO<S>::template store<R>(plane + site, h[i]);
+        for (int i = 0; i < kQ; ++i) StoreIO<S>::template store_nt<R>(dst + (long long)i * P + site, h[i]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            S *__restrict__ plane = dst + (long long)i * P;
+            StoreIO<S>::template store<R>(plane + site, h[i]);
+        }
     }
 }
 

@@ -1,0 +1,40 @@
+// Launch interface of the surrogate's BF16/FP32 kernels (unet_kernels.hip).
+// Tensors are NHWC; 3x3 weights are W[co][tap][ci] with tap = 3*dy + dx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace rlbm {
+
+// out = act(conv3x3(in, w) + bias), zero padding, BF16 in/out, FP32 accumulation (Ci, Co multiples of 16).
+hipError_t conv3x3_forward(const void *in, const void *w, const float *bias, void *out, int B, int H, int W, int Ci,
+                           int Co, bool relu, hipStream_t s);
+// wt[ci][8 - tap][co] = w[co][tap][ci]; the gradient with respect to the input of a 3x3
+// convolution is conv3x3_forward(dout, wt) (no bias, no activation).
+hipError_t conv3x3_adjoint_weights(const void *w, void *wt, int Ci, int Co, hipStream_t s);
+// Pixels per weight-gradient partial; part needs ceil(B*H*W / chunk) * Co * 9 * Ci floats.
+long long conv3x3_wgrad_chunk(long long npix);
+// gw[co][tap][ci] += sum_p dpre[p][co] * in[p + tap][ci] (deterministic two-pass reduction through part).
+hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part, float *gw, int B, int H, int W,
+                                   int Ci, int Co, hipStream_t s);
+// gb[c] += sum_p d[p][c]
+hipError_t channel_sum(const void *d, float *gb, long long npix, int C, hipStream_t s);
+// d *= (out > 0)
+hipError_t relu_backward(void *d, const void *out, long long n, hipStream_t s);
+hipError_t pool_forward(const void *in, void *out, int B, int H, int W, int C, hipStream_t s);
+// dx = dy / 4 broadcast to 2x2 blocks (+ channels [skip_off, skip_off + C) of skip, a B*H*W*skip_c tensor)
+hipError_t pool_backward(const void *dy, const void *skip, int skip_c, int skip_off, void *dx, int B, int H, int W,
+                         int C, hipStream_t s);
+hipError_t up_concat(const void *u, const void *skip, void *cat, int B, int H, int W, int Cu, int Cs, hipStream_t s);
+hipError_t up_backward(const void *dcat, void *du, int B, int H, int W, int Cu, int C, hipStream_t s);
+hipError_t head_forward(const void *x, const void *w, const float *b, float *y, long long npix, int C, int O,
+                        hipStream_t s);
+hipError_t head_backward(const float *dy, const void *x, const void *w, void *dx, float *gw, float *gb, long long npix,
+                         int C, int O, hipStream_t s);
+hipError_t mse(const float *y, const float *t, float *dy, double *part, int nblocks, long long n, hipStream_t s);
+hipError_t adam(float *theta, const float *g, float *m, float *v, void *theta_bf, long long n, float lr, float b1,
+                float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t to_bf16(const float *a, void *b, long long n, hipStream_t s);
+hipError_t to_f32(const void *a, float *b, long long n, hipStream_t s);
+
+}  // namespace rlbm

@@ -1,0 +1,529 @@
+// gfx950 kernels of the convolutional warm-start surrogate (a U-Net):
+// BF16 activations and weights, FP32 accumulation on the matrix cores.
+//
+// Layout: activations NHWC (channels innermost), 3x3 weights W[co][tap][ci]
+// with tap = 3*dy + dx.  A 3x3 convolution is an implicit GEMM
+//   out[pixel, co] = sum_{tap, ci} in[pixel + tap, ci] * W[co, tap, ci]
+// with M = pixels, N = output channels, K = 9 * input channels.  Each
+// wavefront owns a 16-pixel x 16-channel output tile and walks K in steps of
+// 32 (v_mfma_f32_16x16x32_bf16) or 16 (v_mfma_f32_16x16x16_bf16) channels;
+// each lane loads its 8 (or 4) consecutive channels of one pixel and of one
+// weight row with a single vector load.  Operand layout of the 16x16xK
+// matrix instruction (wave64): A[i][k] in lane i + 16*(k / (K/4)), element
+// k % (K/4); B[k][j] likewise with j; C[i][j] in lane j + 16*(i/4), element
+// i % 4.
+#include <hip/hip_runtime.h>
+
+#include "unet_kernels.h"
+
+namespace rlbm {
+namespace {
+
+typedef __bf16 bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+template <int KSTEP>
+struct Mfma;
+template <>
+struct Mfma<32> {
+    typedef bf16x8 vec;
+    __device__ static f32x4 run(vec a, vec b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Mfma<16> {
+    typedef bf16x4 vec;
+    __device__ static f32x4 run(vec a, vec b, f32x4 c)
+    {
+        typedef __attribute__((__vector_size__(4 * sizeof(short)))) short s4;
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a), __builtin_bit_cast(s4, b), c, 0, 0,
+                                                         0);
+    }
+};
+
+// ---------------------------------------------------------------- conv 3x3
+
+// grid.x = B * H * ceil(W / 64), grid.y = Co / 16; 4 wavefronts per block,
+// wavefront w covers pixels x0 + 16 w ... + 15 of one row.
+template <int KSTEP, bool RELU>
+__global__ __launch_bounds__(256) void conv3x3_fwd_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ w,
+                                                          const float *__restrict__ bias, bf16 *__restrict__ out,
+                                                          int H, int W, int Ci, int Co)
+{
+    typedef typename Mfma<KSTEP>::vec vec;
+    constexpr int KPL = KSTEP / 4;  // channels per lane per K step
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tiles_w = (W + 63) / 64;
+    int t = blockIdx.x;
+    const int xt = t % tiles_w;
+    t /= tiles_w;
+    const int y = t % H;
+    const int b = t / H;
+    const int x0 = xt * 64 + wave * 16;
+    if (x0 >= W) return;
+    const int co0 = blockIdx.y * 16;
+    const int r = lane & 15;   // A row (pixel) and B column (channel)
+    const int kq = lane >> 4;  // which group of KPL channels
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    vec zero;
+    for (int q = 0; q < KPL; ++q) zero[q] = (bf16)0.f;
+    for (int dy = 0; dy < 3; ++dy) {
+        const int yy = y + dy - 1;
+        const bool rowok = (unsigned)yy < (unsigned)H;
+        for (int dx = 0; dx < 3; ++dx) {
+            const int xx = x0 + r + dx - 1;
+            const bool ok = rowok && (unsigned)xx < (unsigned)W;
+            const long long pix = ok ? ((long long)b * H + yy) * W + xx : 0;
+            const bf16 *ip = in + pix * Ci + kq * KPL;
+            const bf16 *wp = w + ((long long)(co0 + r) * 9 + dy * 3 + dx) * Ci + kq * KPL;
+            for (int c0 = 0; c0 < Ci; c0 += KSTEP) {
+                const vec a = ok ? *reinterpret_cast<const vec *>(ip + c0) : zero;
+                const vec bv = *reinterpret_cast<const vec *>(wp + c0);
+                acc = Mfma<KSTEP>::run(a, bv, acc);
+            }
+        }
+    }
+    const int j = lane & 15;
+    const float bj = bias ? bias[co0 + j] : 0.f;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int px = x0 + 4 * (lane >> 4) + s;
+        if (px < W) {
+            float v = acc[s] + bj;
+            if (RELU) v = fmaxf(v, 0.f);
+            out[(((long long)b * H + y) * W + px) * Co + co0 + j] = (bf16)v;
+        }
+    }
+}
+
+// wt[ci][8 - tap][co] = w[co][tap][ci]: the weights of the adjoint convolution.
+__global__ void conv3x3_adjoint_weights_kernel(const bf16 *__restrict__ w, bf16 *__restrict__ wt, int Ci, int Co)
+{
+    const long long n = (long long)Co * 9 * Ci;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const int ci = (int)(q % Ci);
+        const int tap = (int)((q / Ci) % 9);
+        const int co = (int)(q / ((long long)Ci * 9));
+        wt[((long long)ci * 9 + (8 - tap)) * Co + co] = w[q];
+    }
+}
+
+// Weight gradient, one partial per pixel chunk:
+// part[chunk][co][tap][ci] = sum over the chunk's pixels p of
+//   dpre[p][co] * in[p shifted by tap][ci].
+// GEMM with M = co (16), N = ci (16), K = pixels (32 per step) for one tap.
+// grid.x = chunks, grid.y = ceil(ntiles / 4) with ntiles = (Co/16)*(Ci/16)*9.
+__global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restrict__ dpre,
+                                                            const bf16 *__restrict__ in, float *__restrict__ part,
+                                                            int B, int H, int W, int Ci, int Co, int chunk_px)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cot = Co / 16, cit = Ci / 16;
+    const int job = blockIdx.y * 4 + wave;
+    if (job >= cot * cit * 9) return;
+    const int tap = job % 9;
+    const int cg = (job / 9) % cit;
+    const int og = job / (9 * cit);
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const long long total = (long long)B * H * W;
+    const long long p_begin = (long long)blockIdx.x * chunk_px;
+    const long long p_end = p_begin + chunk_px < total ? p_begin + chunk_px : total;
+    const int r = lane & 15, kq = lane >> 4;
+    const int co = og * 16 + r, ci = cg * 16 + r;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (long long p0 = p_begin; p0 < p_end; p0 += 32) {
+        bf16x8 a, bv;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const long long p = p0 + kq * 8 + s;
+            bf16 av = (bf16)0.f, bb = (bf16)0.f;
+            if (p < p_end) {
+                av = dpre[p * Co + co];
+                const int x = (int)(p % W);
+                const long long rowid = p / W;
+                const int y = (int)(rowid % H);
+                const int yy = y + dy, xx = x + dx;
+                if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W)
+                    bb = in[(p + (long long)dy * W + dx) * Ci + ci];
+            }
+            a[s] = av;
+            bv[s] = bb;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc, 0, 0, 0);
+    }
+    // C[i = co row][j = ci col] in lane j + 16*(i/4), element i%4
+    const int jj = lane & 15;
+    float *o = part + (long long)blockIdx.x * Co * 9 * Ci;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int ii = 4 * (lane >> 4) + s;
+        o[((long long)(og * 16 + ii) * 9 + tap) * Ci + cg * 16 + jj] = acc[s];
+    }
+}
+
+// g[q] += sum over chunks of part[chunk][q] (fixed order: deterministic).
+__global__ void reduce_chunks_kernel(const float *__restrict__ part, float *__restrict__ g, long long n, int chunks)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int c = 0; c < chunks; ++c) s += part[(long long)c * n + q];
+        g[q] += s;
+    }
+}
+
+// gb[c] += sum over pixels of d[p][c]; one block per channel.
+__global__ __launch_bounds__(256) void channel_sum_kernel(const bf16 *__restrict__ d, float *__restrict__ gb,
+                                                          long long npix, int C)
+{
+    const int c = blockIdx.x;
+    float s = 0.f;
+    for (long long p = threadIdx.x; p < npix; p += blockDim.x) s += (float)d[p * C + c];
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gb[c] += red[0];
+}
+
+// d *= (out > 0): gradient through the ReLU of a layer with output `out`.
+__global__ void relu_backward_kernel(bf16 *__restrict__ d, const bf16 *__restrict__ out, long long n)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        if (!((float)out[q] > 0.f)) d[q] = (bf16)0.f;
+}
+
+// ---------------------------------------------------------------- resampling
+
+// out (B, H/2, W/2, C) = mean of 2x2 blocks of in (B, H, W, C)
+__global__ void pool_fwd_kernel(const bf16 *__restrict__ in, bf16 *__restrict__ out, int B, int H, int W, int C)
+{
+    const int Ho = H / 2, Wo = W / 2;
+    const long long n = (long long)B * Ho * Wo * C;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(q % C);
+        long long t = q / C;
+        const int x = (int)(t % Wo);
+        t /= Wo;
+        const int y = (int)(t % Ho);
+        const int b = (int)(t / Ho);
+        const long long base = (((long long)b * H + 2 * y) * W + 2 * x) * C + c;
+        const float s = (float)in[base] + (float)in[base + C] + (float)in[base + (long long)W * C] +
+                        (float)in[base + (long long)W * C + C];
+        out[q] = (bf16)(0.25f * s);
+    }
+}
+
+// dx (B, H, W, C) = dy / 4 broadcast (+ skip, a (B, H, W, Cs) tensor's channels [off, off + C))
+__global__ void pool_bwd_kernel(const bf16 *__restrict__ dy, const bf16 *__restrict__ skip, int skip_c, int skip_off,
+                                bf16 *__restrict__ dx, int B, int H, int W, int C)
+{
+    const long long n = (long long)B * H * W * C;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(q % C);
+        long long t = q / C;
+        const int x = (int)(t % W);
+        t /= W;
+        const int y = (int)(t % H);
+        const int b = (int)(t / H);
+        float v = 0.25f * (float)dy[(((long long)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
+        if (skip) v += (float)skip[(q / C) * skip_c + skip_off + c];
+        dx[q] = (bf16)v;
+    }
+}
+
+// cat (B, H, W, Cu + Cs): channels [0, Cu) = nearest x2 upsample of u (B, H/2, W/2, Cu),
+// channels [Cu, Cu + Cs) = s (B, H, W, Cs).
+__global__ void up_concat_kernel(const bf16 *__restrict__ u, const bf16 *__restrict__ s, bf16 *__restrict__ cat, int B,
+                                 int H, int W, int Cu, int Cs)
+{
+    const int C = Cu + Cs;
+    const long long n = (long long)B * H * W * C;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(q % C);
+        const long long pix = q / C;
+        const int x = (int)(pix % W);
+        const long long t = pix / W;
+        const int y = (int)(t % H);
+        const int b = (int)(t / H);
+        cat[q] = c < Cu ? u[(((long long)b * (H / 2) + y / 2) * (W / 2) + x / 2) * Cu + c] : s[pix * Cs + (c - Cu)];
+    }
+}
+
+// du (B, H/2, W/2, Cu) = sum over each 2x2 block of dcat's channels [0, Cu)
+__global__ void up_bwd_kernel(const bf16 *__restrict__ dcat, bf16 *__restrict__ du, int B, int H, int W, int Cu,
+                              int C)
+{
+    const int Ho = H / 2, Wo = W / 2;
+    const long long n = (long long)B * Ho * Wo * Cu;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(q % Cu);
+        long long t = q / Cu;
+        const int x = (int)(t % Wo);
+        t /= Wo;
+        const int y = (int)(t % Ho);
+        const int b = (int)(t / Ho);
+        const long long base = (((long long)b * H + 2 * y) * W + 2 * x) * C + c;
+        const float v = (float)dcat[base] + (float)dcat[base + C] + (float)dcat[base + (long long)W * C] +
+                        (float)dcat[base + (long long)W * C + C];
+        du[q] = (bf16)v;
+    }
+}
+
+// ---------------------------------------------------------------- head, loss, optimiser
+
+// y[p][o] = b[o] + sum_c x[p][c] * w[o][c]   (1x1 convolution, FP32 output)
+__global__ void head_fwd_kernel(const bf16 *__restrict__ x, const bf16 *__restrict__ w, const float *__restrict__ b,
+                                float *__restrict__ y, long long npix, int C, int O)
+{
+    const long long n = npix * O;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const int o = (int)(q % O);
+        const long long p = q / O;
+        float s = b[o];
+        for (int c = 0; c < C; ++c) s += (float)x[p * C + c] * (float)w[o * C + c];
+        y[q] = s;
+    }
+}
+
+// dx[p][c] = sum_o dy[p][o] * w[o][c]  (BF16 output)
+__global__ void head_bwd_data_kernel(const float *__restrict__ dy, const bf16 *__restrict__ w, bf16 *__restrict__ dx,
+                                     long long npix, int C, int O)
+{
+    const long long n = npix * C;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const int c = (int)(q % C);
+        const long long p = q / C;
+        float s = 0.f;
+        for (int o = 0; o < O; ++o) s += dy[p * O + o] * (float)w[o * C + c];
+        dx[q] = (bf16)s;
+    }
+}
+
+// Head parameter gradient: one block per output entry (o, c) of W (c < C)
+// or of the bias (c == C): gW[o][c] += sum_p dy[p][o] x[p][c], gb[o] += sum_p dy[p][o].
+__global__ __launch_bounds__(256) void head_wgrad_kernel(const float *__restrict__ dy, const bf16 *__restrict__ x,
+                                                         float *__restrict__ gw, float *__restrict__ gb,
+                                                         long long npix, int C, int O)
+{
+    const int o = blockIdx.x / (C + 1), c = blockIdx.x % (C + 1);
+    float s = 0.f;
+    for (long long p = threadIdx.x; p < npix; p += blockDim.x) s += dy[p * O + o] * (c < C ? (float)x[p * C + c] : 1.f);
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (c < C)
+            gw[o * C + c] += red[0];
+        else
+            gb[o] += red[0];
+    }
+}
+
+// Mean squared error: per-block partial sums of (y - t)^2 and dy = 2 (y - t) / n.
+__global__ __launch_bounds__(256) void mse_kernel(const float *__restrict__ y, const float *__restrict__ t,
+                                                  float *__restrict__ dy, double *__restrict__ part, long long n)
+{
+    double s = 0.0;
+    const float scale = 2.0f / (float)n;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const float d = y[q] - t[q];
+        s += (double)d * d;
+        if (dy) dy[q] = scale * d;
+    }
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Adam with bias correction; keeps the FP32 master parameters and refreshes
+// their BF16 copies (conv weights) in the same pass.
+__global__ void adam_kernel(float *__restrict__ theta, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, bf16 *__restrict__ theta_bf, long long n, float lr, float b1,
+                            float b2, float eps, float c1, float c2)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const float gq = g[q];
+        const float mq = b1 * m[q] + (1.f - b1) * gq;
+        const float vq = b2 * v[q] + (1.f - b2) * gq * gq;
+        m[q] = mq;
+        v[q] = vq;
+        const float th = theta[q] - lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+        theta[q] = th;
+        theta_bf[q] = (bf16)th;
+    }
+}
+
+__global__ void to_bf16_kernel(const float *__restrict__ a, bf16 *__restrict__ b, long long n)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        b[q] = (bf16)a[q];
+}
+
+__global__ void to_f32_kernel(const bf16 *__restrict__ a, float *__restrict__ b, long long n)
+{
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        b[q] = (float)a[q];
+}
+
+inline unsigned grid_for(long long n, int block = 256)
+{
+    long long g = (n + block - 1) / block;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t conv3x3_forward(const void *in, const void *w, const float *bias, void *out, int B, int H, int W, int Ci,
+                           int Co, bool relu, hipStream_t s)
+{
+    if (Ci % 16 || Co % 16 || B < 1 || H < 1 || W < 1) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(B * H * ((W + 63) / 64)), (unsigned)(Co / 16));
+    const bf16 *i = static_cast<const bf16 *>(in), *wt = static_cast<const bf16 *>(w);
+    bf16 *o = static_cast<bf16 *>(out);
+    if (Ci % 32 == 0) {
+        if (relu)
+            hipLaunchKernelGGL((conv3x3_fwd_kernel<32, true>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+        else
+            hipLaunchKernelGGL((conv3x3_fwd_kernel<32, false>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+    } else {
+        if (relu)
+            hipLaunchKernelGGL((conv3x3_fwd_kernel<16, true>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+        else
+            hipLaunchKernelGGL((conv3x3_fwd_kernel<16, false>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+    }
+    return hipGetLastError();
+}
+
+hipError_t conv3x3_adjoint_weights(const void *w, void *wt, int Ci, int Co, hipStream_t s)
+{
+    hipLaunchKernelGGL(conv3x3_adjoint_weights_kernel, dim3(grid_for((long long)Co * 9 * Ci)), dim3(256), 0, s,
+                       static_cast<const bf16 *>(w), static_cast<bf16 *>(wt), Ci, Co);
+    return hipGetLastError();
+}
+
+long long conv3x3_wgrad_chunk(long long npix) { return npix < 4096 ? ((npix + 31) / 32) * 32 : 4096; }
+
+hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part, float *gw, int B, int H, int W,
+                                   int Ci, int Co, hipStream_t s)
+{
+    if (Ci % 16 || Co % 16) return hipErrorInvalidValue;
+    const long long npix = (long long)B * H * W;
+    const long long chunk = conv3x3_wgrad_chunk(npix);
+    const int chunks = (int)((npix + chunk - 1) / chunk);
+    const int jobs = (Co / 16) * (Ci / 16) * 9;
+    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(chunks, (jobs + 3) / 4), dim3(256), 0, s,
+                       static_cast<const bf16 *>(dpre), static_cast<const bf16 *>(in), part, B, H, W, Ci, Co,
+                       (int)chunk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long n = (long long)Co * 9 * Ci;
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(grid_for(n)), dim3(256), 0, s, part, gw, n, chunks);
+    return hipGetLastError();
+}
+
+hipError_t channel_sum(const void *d, float *gb, long long npix, int C, hipStream_t s)
+{
+    hipLaunchKernelGGL(channel_sum_kernel, dim3(C), dim3(256), 0, s, static_cast<const bf16 *>(d), gb, npix, C);
+    return hipGetLastError();
+}
+
+hipError_t relu_backward(void *d, const void *out, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(relu_backward_kernel, dim3(grid_for(n)), dim3(256), 0, s, static_cast<bf16 *>(d),
+                       static_cast<const bf16 *>(out), n);
+    return hipGetLastError();
+}
+
+hipError_t pool_forward(const void *in, void *out, int B, int H, int W, int C, hipStream_t s)
+{
+    hipLaunchKernelGGL(pool_fwd_kernel, dim3(grid_for((long long)B * H * W * C / 4)), dim3(256), 0, s,
+                       static_cast<const bf16 *>(in), static_cast<bf16 *>(out), B, H, W, C);
+    return hipGetLastError();
+}
+
+hipError_t pool_backward(const void *dy, const void *skip, int skip_c, int skip_off, void *dx, int B, int H, int W,
+                         int C, hipStream_t s)
+{
+    hipLaunchKernelGGL(pool_bwd_kernel, dim3(grid_for((long long)B * H * W * C)), dim3(256), 0, s,
+                       static_cast<const bf16 *>(dy), static_cast<const bf16 *>(skip), skip_c, skip_off,
+                       static_cast<bf16 *>(dx), B, H, W, C);
+    return hipGetLastError();
+}
+
+hipError_t up_concat(const void *u, const void *skip, void *cat, int B, int H, int W, int Cu, int Cs, hipStream_t s)
+{
+    hipLaunchKernelGGL(up_concat_kernel, dim3(grid_for((long long)B * H * W * (Cu + Cs))), dim3(256), 0, s,
+                       static_cast<const bf16 *>(u), static_cast<const bf16 *>(skip), static_cast<bf16 *>(cat), B, H,
+                       W, Cu, Cs);
+    return hipGetLastError();
+}
+
+hipError_t up_backward(const void *dcat, void *du, int B, int H, int W, int Cu, int C, hipStream_t s)
+{
+    hipLaunchKernelGGL(up_bwd_kernel, dim3(grid_for((long long)B * H * W * Cu / 4)), dim3(256), 0, s,
+                       static_cast<const bf16 *>(dcat), static_cast<bf16 *>(du), B, H, W, Cu, C);
+    return hipGetLastError();
+}
+
+hipError_t head_forward(const void *x, const void *w, const float *b, float *y, long long npix, int C, int O,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(head_fwd_kernel, dim3(grid_for(npix * O)), dim3(256), 0, s, static_cast<const bf16 *>(x),
+                       static_cast<const bf16 *>(w), b, y, npix, C, O);
+    return hipGetLastError();
+}
+
+hipError_t head_backward(const float *dy, const void *x, const void *w, void *dx, float *gw, float *gb, long long npix,
+                         int C, int O, hipStream_t s)
+{
+    hipLaunchKernelGGL(head_bwd_data_kernel, dim3(grid_for(npix * C)), dim3(256), 0, s, dy,
+                       static_cast<const bf16 *>(w), static_cast<bf16 *>(dx), npix, C, O);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(head_wgrad_kernel, dim3(O * (C + 1)), dim3(256), 0, s, dy, static_cast<const bf16 *>(x), gw, gb,
+                       npix, C, O);
+    return hipGetLastError();
+}
+
+hipError_t mse(const float *y, const float *t, float *dy, double *part, int nblocks, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(mse_kernel, dim3(nblocks), dim3(256), 0, s, y, t, dy, part, n);
+    return hipGetLastError();
+}
+
+hipError_t adam(float *theta, const float *g, float *m, float *v, void *theta_bf, long long n, float lr, float b1,
+                float b2, float eps, float c1, float c2, hipStream_t s)
+{
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, s, theta, g, m, v, static_cast<bf16 *>(theta_bf),
+                       n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t to_bf16(const float *a, void *b, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid_for(n)), dim3(256), 0, s, a, static_cast<bf16 *>(b), n);
+    return hipGetLastError();
+}
+
+hipError_t to_f32(const void *a, float *b, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, static_cast<const bf16 *>(a), b, n);
+    return hipGetLastError();
+}
+
+}  // namespace rlbm

@@ -1,0 +1,148 @@
+"""Warm-start surrogate pipeline: data from the solver, training, warm start.
+
+Everything numerical runs in librlbm.so (the batched FP64 solver for data,
+the BF16 U-Net kernels for training and inference); this module only
+arranges batches and bookkeeping.
+
+* Encoding of a sample (``encode``): an H x W x 16 float32 image with
+  channels 0: fluid mask (1), 1: source contact (1 on the bottom row inside
+  its span), 2: drain contact, 3: tau, 4: log10(drive) + 5, 5..15: 0.
+* Targets (``targets``): the steady state in linear response,
+  ((n - 1)/F, vx/F, vy/F), with F the drive magnitude.
+* Warm start (``warm_start``): n = 1 + F p0, v = F (p1, p2), T = 1; the
+  prediction is rejected (cold start instead) if any value is non-finite,
+  n <= 0 or |v| >= 1.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import _binding as B
+from . import workloads
+
+CIN = 16
+COUT = 3
+
+
+def encode(w) -> np.ndarray:
+    H, W = w["ny"], w["nx"]
+    x = np.zeros((H, W, CIN), dtype=np.float32)
+    x[..., 0] = 1.0
+    for k, c in enumerate(w["contacts"][:2]):
+        if c["edge"] == "bottom":
+            x[0, c["start"]:c["start"] + c["width"], 1 + k] = 1.0
+    x[..., 3] = w["tau"]
+    x[..., 4] = np.log10(abs(w["F"][0]) + abs(w["F"][1])) + 5.0
+    return x
+
+
+def drive(w) -> float:
+    return float(np.hypot(*w["F"]))
+
+
+def targets(w, fields) -> np.ndarray:
+    F = drive(w)
+    return np.stack([(fields["n"] - 1.0) / F, fields["vx"] / F, fields["vy"] / F], axis=-1).astype(np.float32)
+
+
+def decode(w, pred: np.ndarray):
+    """(n, vx, vy) from a prediction, or None when it is unusable."""
+    F = drive(w)
+    n = 1.0 + F * pred[..., 0].astype(np.float64)
+    vx = F * pred[..., 1].astype(np.float64)
+    vy = F * pred[..., 2].astype(np.float64)
+    if not (np.isfinite(n).all() and np.isfinite(vx).all() and np.isfinite(vy).all()):
+        return None
+    if (n <= 0).any() or (vx * vx + vy * vy >= 1.0).any():
+        return None
+    return n, vx, vy
+
+
+def solve_batch(samples, max_steps, check_every=100, tol=1e-8, storage="f64", init=None):
+    """Run samples to steady state with the batched solver.  init: optional
+    per-sample (n, vx, vy) warm starts (None entries start cold).  Returns
+    (fields list, steps array, residuals array, seconds)."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt = B.Batch(samples, storage)
+    if init is not None:
+        for L, st in zip(bt.lattices, init):
+            if st is not None:
+                n, vx, vy = st
+                L.init_fields(n, np.ones_like(n), vx, vy)
+    steps, r = bt.step_until(max_steps, check_every, tol)
+    fields = [L.read_fields() for L in bt.lattices]
+    bt.close()
+    torch.cuda.synchronize()
+    return fields, steps, r, time.perf_counter() - t0
+
+
+def generate(count, size=256, seed_offset=0, max_steps=300_000, tol=1e-8, chunk=256, log=print):
+    """Steady states of `count` samples of the uneven-sample generator at a
+    fixed size (FP64, residual tol over 100 steps)."""
+    all_samples = workloads.batch_samples(seed_offset + count, fixed_size=(size, size))[seed_offset:]
+    X, Y, info = [], [], []
+    for i in range(0, count, chunk):
+        part = all_samples[i:i + chunk]
+        fields, steps, r, secs = solve_batch(part, max_steps, tol=tol)
+        log(f"generated {i + len(part)}/{count}: steps median {int(np.median(steps))} max {int(steps.max())}, "
+            f"converged {(r < tol).sum()}/{len(part)}, {secs:.1f} s")
+        for w, f, s, rr in zip(part, fields, steps, r):
+            X.append(encode(w))
+            Y.append(targets(w, f))
+            info.append(dict(steps=int(s), residual=float(rr), tau=w["tau"], F=drive(w)))
+    return np.stack(X), np.stack(Y), info
+
+
+def train(net, X, Y, epochs, batch, lr=1e-3, log=print, seed=0):
+    """Minibatch Adam on (X, Y) held on the device; returns the loss curve."""
+    import torch
+
+    rng = np.random.default_rng(seed)
+    n = X.shape[0]
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.from_numpy(Y).cuda()
+    out = torch.empty((batch,) + Y.shape[1:], dtype=torch.float32, device="cuda")
+    dy = torch.empty_like(out)
+    curve = []
+    for ep in range(epochs):
+        order = rng.permutation(n)
+        tot = 0.0
+        nb = 0
+        for k in range(0, n - batch + 1, batch):
+            idx = torch.from_numpy(order[k:k + batch]).cuda()
+            xb = Xd.index_select(0, idx).contiguous()
+            yb = Yd.index_select(0, idx).contiguous()
+            net.forward(xb, out)
+            tot += net.mse(out, yb, dy)
+            nb += 1
+            net.zero_grad()
+            net.backward(dy)
+            net.adam_step(lr * (0.5 * (1 + np.cos(np.pi * ep / epochs))))
+        curve.append(tot / max(nb, 1))
+        log(f"epoch {ep}: loss {curve[-1]:.4g}")
+    return curve
+
+
+def predict(net, X, batch):
+    import torch
+
+    preds = []
+    out = torch.empty((batch,) + X.shape[1:3] + (COUT,), dtype=torch.float32, device="cuda")
+    for k in range(0, X.shape[0], batch):
+        xb = torch.from_numpy(X[k:k + batch]).cuda()
+        nb = xb.shape[0]
+        if nb < batch:
+            xb = torch.cat([xb, torch.zeros((batch - nb,) + xb.shape[1:], device="cuda")])
+        net.forward(xb.contiguous(), out)
+        preds.append(out[:nb].cpu().numpy())
+    return np.concatenate(preds)
+
+
+def warm_start_inits(samples, preds):
+    """Decoded warm starts, None where the prediction is rejected."""
+    return [decode(w, p) for w, p in zip(samples, preds)]

@@ -1,0 +1,151 @@
+"""GPU tests of the surrogate's BF16 kernels against the FP64 reference net.
+
+Every kernel is compared on inputs that are first rounded to BF16 on the
+host, so both sides see the same operands: a single convolution then differs
+only by FP32 accumulation order plus the final BF16 rounding of its output
+(relative 2^-9), the weight gradient only by FP32 accumulation.  Through the
+whole network every activation is re-rounded to BF16, so end-to-end outputs
+and gradients are compared at the percent level.  A short Adam run on a
+fixed batch must drive the loss down.
+"""
+import numpy as np
+import pytest
+
+from oracle import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _bf16_round(a):
+    """Round float64 -> bfloat16 -> float64 (torch implements RNE)."""
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _dev_bf16(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(torch.bfloat16).cuda().contiguous()
+
+
+def _host(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("ci,co,relu", [(16, 16, True), (48, 32, False), (64, 16, True), (32, 48, False)])
+def test_conv3x3_forward_matches_reference(ci, co, relu):
+    import paper_1804_02418_amd as rl
+
+    torch = _torch()
+    rng = np.random.default_rng(ci * 100 + co)
+    B, H, W = 2, 24, 40
+    x = _bf16_round(rng.normal(size=(B, H, W, ci)))
+    w = _bf16_round(rng.normal(size=(co, 3, 3, ci)) / np.sqrt(9 * ci))
+    b = rng.normal(size=co).astype(np.float32)
+    y = torch.empty((B, H, W, co), dtype=torch.bfloat16, device="cuda")
+    rl.conv3x3_forward(_dev_bf16(x), _dev_bf16(w), torch.from_numpy(b).cuda(), y, relu=relu)
+    torch.cuda.synchronize()
+    ref = S.conv(x, w, b.astype(np.float64))
+    if relu:
+        ref = np.maximum(ref, 0)
+    got = _host(y)
+    err = np.abs(got - ref).max()
+    print("conv fwd", ci, co, relu, "max err", err, "max |ref|", np.abs(ref).max(), flush=True)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("ci,co", [(16, 32), (48, 16)])
+def test_conv3x3_backward_kernels_match_reference(ci, co):
+    import paper_1804_02418_amd as rl
+
+    torch = _torch()
+    rng = np.random.default_rng(7 + ci)
+    B, H, W = 2, 16, 32
+    x = _bf16_round(rng.normal(size=(B, H, W, ci)))
+    w = _bf16_round(rng.normal(size=(co, 3, 3, ci)) / np.sqrt(9 * ci))
+    dy = _bf16_round(rng.normal(size=(B, H, W, co)))
+    rdx, rdw, rdb = S.conv_backward(x, w, dy)
+    dx = torch.empty((B, H, W, ci), dtype=torch.bfloat16, device="cuda")
+    rl.conv3x3_backward_data(_dev_bf16(dy), _dev_bf16(w), dx)
+    gw = torch.zeros((co, 3, 3, ci), dtype=torch.float32, device="cuda")
+    gb = torch.zeros(co, dtype=torch.float32, device="cuda")
+    rl.conv3x3_backward_weight(_dev_bf16(dy), _dev_bf16(x), gw, gb)
+    torch.cuda.synchronize()
+    gdx, gdw, gdb = _host(dx), _host(gw), _host(gb)
+    print("bwd data err", np.abs(gdx - rdx).max(), "weight err", np.abs(gdw - rdw).max() / np.abs(rdw).max(), flush=True)
+    assert np.all(np.abs(gdx - rdx) <= 2.0 ** -8 * np.abs(rdx) + 1e-5 * np.abs(rdx).max())
+    assert np.abs(gdw - rdw).max() <= 1e-5 * np.abs(rdw).max()
+    assert np.abs(gdb - rdb).max() <= 1e-5 * np.abs(rdb).max()
+
+
+def _net_case(seed=3, B=2, H=32, W=32):
+    base, cin, cout = 16, 16, 3
+    rng = np.random.default_rng(seed)
+    theta = S.he_init(base, cin, cout, seed).astype(np.float32)
+    theta[-cout:] = rng.normal(size=cout)  # non-zero head bias
+    x = rng.normal(size=(B, H, W, cin))
+    x[..., 5:] = 0.0
+    t = rng.normal(size=(B, H, W, cout))
+    return base, cin, cout, theta, x, t
+
+
+def test_network_forward_and_backward_match_reference():
+    import paper_1804_02418_amd as rl
+
+    torch = _torch()
+    base, cin, cout, theta, x, t = _net_case()
+    B, H, W = x.shape[:3]
+    net = rl.UNet(base, cin, cout, H, W, max_batch=B)
+    net.set_params(theta)
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    td = torch.from_numpy(t.astype(np.float32)).cuda()
+    y = torch.empty((B, H, W, cout), dtype=torch.float32, device="cuda")
+    dy = torch.empty_like(y)
+    net.forward(xd, y)
+    loss = net.mse(y, td, dy)
+    net.zero_grad()
+    net.backward(dy)
+    g = net.get_grads().astype(np.float64)
+    # reference on the BF16-rounded parameters and input (the GPU computes with those)
+    ref = S.ReferenceUNet(base, cin, cout)
+    theta_b = _bf16_round(theta)
+    yr, cache = ref.forward(theta_b, _bf16_round(x))
+    lr_, dyr = S.ReferenceUNet.mse(yr, t)
+    gr, _ = ref.backward(theta_b, cache, dyr)
+    got = y.cpu().numpy().astype(np.float64)
+    fwd_err = np.abs(got - yr).max() / np.abs(yr).max()
+    cos = float(g @ gr / (np.linalg.norm(g) * np.linalg.norm(gr)))
+    rel = float(np.linalg.norm(g - gr) / np.linalg.norm(gr))
+    print("unet fwd rel err", fwd_err, "loss", loss, lr_, "grad cosine", cos, "grad rel L2", rel, flush=True)
+    assert fwd_err < 3e-2
+    assert abs(loss - lr_) < 2e-2 * lr_
+    assert cos > 0.999 and rel < 5e-2
+
+
+def test_adam_training_reduces_loss():
+    import paper_1804_02418_amd as rl
+
+    torch = _torch()
+    base, cin, cout, theta, x, t = _net_case(seed=5, B=4, H=32, W=32)
+    t = 0.1 * np.tanh(t)
+    B, H, W = x.shape[:3]
+    net = rl.UNet(base, cin, cout, H, W, max_batch=B)
+    net.set_params(theta)
+    xd = torch.from_numpy(x.astype(np.float32)).cuda()
+    td = torch.from_numpy(t.astype(np.float32)).cuda()
+    y = torch.empty((B, H, W, cout), dtype=torch.float32, device="cuda")
+    dy = torch.empty_like(y)
+    losses = []
+    for _ in range(60):
+        net.forward(xd, y)
+        losses.append(net.mse(y, td, dy))
+        net.zero_grad()
+        net.backward(dy)
+        net.adam_step(1e-3)
+    print("losses", losses[0], losses[10], losses[-1], flush=True)
+    assert losses[-1] < 0.5 * losses[0]
