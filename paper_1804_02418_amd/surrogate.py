@@ -7,11 +7,15 @@ arranges batches and bookkeeping.
 * Encoding of a sample (``encode``): an H x W x 16 float32 image with
   channels 0: fluid mask (1), 1: source contact (1 on the bottom row inside
   its span), 2: drain contact, 3: tau, 4: log10(drive) + 5, 5..15: 0.
-* Targets (``targets``): the steady state in linear response,
-  ((n - 1)/F, vx/F, vy/F), with F the drive magnitude.
-* Warm start (``warm_start``): n = 1 + F p0, v = F (p1, p2), T = 1; the
-  prediction is rejected (cold start instead) if any value is non-finite,
-  n <= 0 or |v| >= 1.
+* Targets (``targets``): the steady state in linear response, scaled the
+  way slow viscous flow scales: ((n - 1)/F, vx (tau - 1/2)/F,
+  vy (tau - 1/2)/F), with F the drive magnitude (the velocity of a Stokes
+  flow driven by F goes as F / viscosity, and the viscosity as tau - 1/2).
+  The network is trained on these divided by per-channel scales (the
+  training set's standard deviations).
+* Warm start (``decode``): n = 1 + F p0, v = F (p1, p2) / (tau - 1/2),
+  T = 1; the prediction is rejected (cold start instead) if any value is
+  non-finite, n <= 0 or |v| >= 1.
 """
 from __future__ import annotations
 
@@ -44,15 +48,18 @@ def drive(w) -> float:
 
 def targets(w, fields) -> np.ndarray:
     F = drive(w)
-    return np.stack([(fields["n"] - 1.0) / F, fields["vx"] / F, fields["vy"] / F], axis=-1).astype(np.float32)
+    g = w["tau"] - 0.5
+    return np.stack([(fields["n"] - 1.0) / F, fields["vx"] * g / F, fields["vy"] * g / F],
+                    axis=-1).astype(np.float32)
 
 
 def decode(w, pred: np.ndarray):
-    """(n, vx, vy) from a prediction, or None when it is unusable."""
+    """(n, vx, vy) from an (unscaled) prediction, or None when it is unusable."""
     F = drive(w)
+    g = w["tau"] - 0.5
     n = 1.0 + F * pred[..., 0].astype(np.float64)
-    vx = F * pred[..., 1].astype(np.float64)
-    vy = F * pred[..., 2].astype(np.float64)
+    vx = F / g * pred[..., 1].astype(np.float64)
+    vy = F / g * pred[..., 2].astype(np.float64)
     if not (np.isfinite(n).all() and np.isfinite(vx).all() and np.isfinite(vy).all()):
         return None
     if (n <= 0).any() or (vx * vx + vy * vy >= 1.0).any():
@@ -141,6 +148,10 @@ def predict(net, X, batch):
         net.forward(xb.contiguous(), out)
         preds.append(out[:nb].cpu().numpy())
     return np.concatenate(preds)
+
+
+def channel_scales(Y) -> np.ndarray:
+    return np.maximum(Y.reshape(-1, Y.shape[-1]).std(axis=0), 1e-12).astype(np.float32)
 
 
 def warm_start_inits(samples, preds):

@@ -55,15 +55,17 @@ def main(argv=None):
     log(f"training on {keep.sum()} converged samples of {len(info_tr)}")
 
     net = B.UNet(16, S.CIN, S.COUT, args.size, args.size, max_batch=args.batch, seed=1)
+    scale = S.channel_scales(Ytr[keep])
+    log(f"target scales {scale}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    curve = S.train(net, Xtr[keep], Ytr[keep], args.epochs, args.batch, args.lr, log=log)
+    curve = S.train(net, Xtr[keep], Ytr[keep] / scale, args.epochs, args.batch, args.lr, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    preds = S.predict(net, Xte, args.batch)
+    preds = S.predict(net, Xte, args.batch) * scale
     torch.cuda.synchronize()
     t_infer = time.perf_counter() - t0
     err = np.sqrt(((preds - Yte) ** 2).mean(axis=(1, 2, 3)) / (Yte ** 2).mean(axis=(1, 2, 3)))
@@ -76,7 +78,8 @@ def main(argv=None):
     report = {
         "samples": {"train": int(keep.sum()), "heldout": args.heldout, "size": args.size},
         "train": {"epochs": args.epochs, "batch": args.batch, "lr": args.lr, "seconds": round(t_train, 2),
-                  "loss_first": curve[0], "loss_last": curve[-1], "params": net.nparam},
+                  "loss_first": curve[0], "loss_last": curve[-1], "params": net.nparam,
+                  "target_scales": [float(v) for v in scale]},
         "heldout_prediction_rel_rms_error": {"median": float(np.median(err)), "max": float(err.max())},
         "cold": {"steps_median": float(np.median(steps_c2)), "steps_mean": float(steps_c2.mean()),
                  "seconds_batch": round(t_cold, 2), "converged": int((r_c2 < args.tol).sum())},
@@ -88,7 +91,7 @@ def main(argv=None):
     }
     log(json.dumps(report))
     if args.out:
-        np.savez(args.out, theta=net.get_params(), base=16, cin=S.CIN, cout=S.COUT, size=args.size,
+        np.savez(args.out, theta=net.get_params(), scale=scale, base=16, cin=S.CIN, cout=S.COUT, size=args.size,
                  loss=np.array(curve))
     if args.report:
         with open(args.report, "w") as fh:
