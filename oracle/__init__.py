@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
     L.orc_lattice_fields.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.orc_lattice_fields.restype = ctypes.c_int
     L.orc_lattice_init.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_lattice_set_lca.argtypes = [vp, ctypes.c_double]
     return L
 
 
@@ -193,7 +194,7 @@ class Lattice:
     """
 
     def __init__(self, stencil: Stencil, nx: int, ny: int, *, periodic_x=False, periodic_y=False,
-                 contacts=(), solid=None, tau=1.0, F=(0.0, 0.0)):
+                 contacts=(), solid=None, tau=1.0, F=(0.0, 0.0), cg=None):
         self.st = stencil
         self.nx, self.ny = int(nx), int(ny)
         self.tau = float(tau)
@@ -215,6 +216,9 @@ class Lattice:
                                         _ptr(state), sp, self.tau, self.F[0], self.F[1])
         if not self._h:
             raise ValueError("invalid lattice description")
+        # local-capacitance force -(1/C_g) grad n (None or inf: off)
+        if cg is not None and np.isfinite(cg):
+            lib().orc_lattice_set_lca(self._h, 1.0 / float(cg))
         self.f = np.zeros((Q, self.ny, self.nx), dtype=np.float64)
         self.t = 0
 

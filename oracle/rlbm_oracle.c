@@ -21,6 +21,10 @@
  * table of Appendix A polynomials at the nodes and the two 16x16 force
  * matrices; Appendix B (the projections a^(k)) is transcribed here.
  *
+ * The external force of step 6 is the uniform drive, plus, when switched
+ * on, the local-capacitance term of Sec. 3 (Eq. lca) taken from the density
+ * of the previous state (orc_lattice_set_lca).
+ *
  * Storage: populations are SoA, f[i * ny * nx + y * nx + x], i = 4*d + j.
  * The state kept between steps is the pre-collision f(t).
  */
@@ -55,6 +59,8 @@ typedef struct {
     double feq_c[MAXC][Q];
     unsigned char *solid;   /* NULL or nx*ny, 1 = solid */
     double tau, Fx, Fy;
+    double inv_cg;          /* 1/C_g of the local-capacitance force (0: off) */
+    double *n_prev;         /* density of the previous state (for the LCA force) */
 } orc_lattice;
 
 /* ---------------------------------------------------------------- stencil */
@@ -269,7 +275,67 @@ void orc_lattice_free(orc_lattice *L)
 {
     if (!L) return;
     free(L->solid);
+    free(L->n_prev);
     free(L);
+}
+
+/* Local-capacitance electrostatics (Sec. 3, Eq. lca): phi = -e n / C_g.  The
+ * force per particle is taken as F = -(e^2 / C_g) grad n (Coulomb repulsion
+ * pushes carriers out of denser regions), with e = 1 in lattice units, so the
+ * total force on a site is the uniform drive plus -(1/C_g) grad n.  grad n is
+ * the central difference of the density of the previous state; a neighbour
+ * that is off the lattice (no periodic wrap) or solid takes the site's own
+ * density.  inv_cg = 0 switches the term off (C_g = infinity). */
+void orc_lattice_set_lca(orc_lattice *L, double inv_cg)
+{
+    L->inv_cg = inv_cg;
+    free(L->n_prev);
+    L->n_prev = NULL;
+}
+
+int orc_lattice_fields(const orc_lattice *L, const double *f, double *n, double *vx, double *vy,
+                       double *eps, double *T);
+
+/* Density of the state f into n (nx*ny). */
+static int density_of(const orc_lattice *L, const double *f, double *n)
+{
+    const size_t P = (size_t)L->nx * L->ny;
+    double *tmp = (double *)malloc(4 * P * sizeof(double));
+    if (!tmp) return -2;
+    orc_lattice_fields(L, f, n, tmp, tmp + P, tmp + 2 * P, tmp + 3 * P);
+    free(tmp);
+    return 0;
+}
+
+/* With the force on and no previous density yet, the first collision takes
+ * the density of the state it collides. */
+static int ensure_n_prev(orc_lattice *L, const double *f)
+{
+    if (L->inv_cg == 0.0 || L->n_prev) return 0;
+    L->n_prev = (double *)malloc((size_t)L->nx * L->ny * sizeof(double));
+    if (!L->n_prev) return -2;
+    return density_of(L, f, L->n_prev);
+}
+
+static double n_at(const orc_lattice *L, const double *n, int x, int y, int x0, int y0)
+{
+    if (L->periodic_x) x = ((x % L->nx) + L->nx) % L->nx;
+    if (L->periodic_y) y = ((y % L->ny) + L->ny) % L->ny;
+    if (x < 0 || x >= L->nx || y < 0 || y >= L->ny) return n[(size_t)y0 * L->nx + x0];
+    if (L->solid && L->solid[(size_t)y * L->nx + x]) return n[(size_t)y0 * L->nx + x0];
+    return n[(size_t)y * L->nx + x];
+}
+
+static void site_force(const orc_lattice *L, int x, int y, double *Fx, double *Fy)
+{
+    *Fx = L->Fx;
+    *Fy = L->Fy;
+    if (L->inv_cg == 0.0 || !L->n_prev) return;
+    const double *n = L->n_prev;
+    const double gx = 0.5 * (n_at(L, n, x + 1, y, x, y) - n_at(L, n, x - 1, y, x, y));
+    const double gy = 0.5 * (n_at(L, n, x, y + 1, x, y) - n_at(L, n, x, y - 1, x, y));
+    *Fx -= L->inv_cg * gx;
+    *Fy -= L->inv_cg * gy;
 }
 
 static int is_solid(const orc_lattice *L, int x, int y)
@@ -301,8 +367,9 @@ static void get_site(const orc_lattice *L, const double *f, size_t site, double 
 }
 
 /* Post-collision populations at every fluid site (solid sites copied). */
-int orc_lattice_collide(const orc_lattice *L, const double *f, double *fstar)
+int orc_lattice_collide(orc_lattice *L, const double *f, double *fstar)
 {
+    if (ensure_n_prev(L, f)) return -2;
     const size_t plane = (size_t)L->nx * L->ny;
     int bad = 0;
 #pragma omp parallel for schedule(static) reduction(+ : bad)
@@ -311,9 +378,11 @@ int orc_lattice_collide(const orc_lattice *L, const double *f, double *fstar)
         for (int x = 0; x < L->nx; ++x) {
             const size_t site = (size_t)y * L->nx + x;
             get_site(L, f, site, in);
+            double Fx, Fy;
+            site_force(L, x, y, &Fx, &Fy);
             if (is_solid(L, x, y)) {
                 for (int i = 0; i < Q; ++i) out[i] = in[i];
-            } else if (orc_collide(L->st, in, L->tau, L->Fx, L->Fy, out)) {
+            } else if (orc_collide(L->st, in, L->tau, Fx, Fy, out)) {
                 bad += 1;
                 for (int i = 0; i < Q; ++i) out[i] = NAN;
             }
@@ -357,18 +426,29 @@ void orc_lattice_stream(const orc_lattice *L, const double *fstar, double *fnew)
     }
 }
 
-/* Advance the pre-collision state f by nsteps steps in place. */
-int orc_lattice_run(const orc_lattice *L, double *f, int64_t nsteps)
+/* Advance the pre-collision state f by nsteps steps in place.  With the LCA
+ * force on, the collision of f(t) uses grad n of f(t-1) (of f(0) itself at
+ * t = 0), which the lattice keeps between calls in n_prev. */
+int orc_lattice_run(orc_lattice *L, double *f, int64_t nsteps)
 {
     const size_t n = (size_t)Q * L->nx * L->ny;
+    const size_t P = (size_t)L->nx * L->ny;
     double *fstar = (double *)malloc(n * sizeof(double));
     if (!fstar) return -2;
+    double *ncur = NULL;
+    if (L->inv_cg != 0.0) {
+        ncur = (double *)malloc(P * sizeof(double));
+        if (!ncur || ensure_n_prev(L, f)) { free(fstar); free(ncur); return -2; }
+    }
     int bad = 0;
     for (int64_t t = 0; t < nsteps; ++t) {
+        if (ncur) density_of(L, f, ncur);
         bad += orc_lattice_collide(L, f, fstar);
         orc_lattice_stream(L, fstar, f);
+        if (ncur) memcpy(L->n_prev, ncur, P * sizeof(double));
     }
     free(fstar);
+    free(ncur);
     return bad;
 }
 
@@ -394,9 +474,11 @@ int orc_lattice_fields(const orc_lattice *L, const double *f, double *n, double 
 }
 
 /* f = f^eq(n, T, v) at every site (initial state). */
-void orc_lattice_init(const orc_lattice *L, const double *n, const double *T, const double *vx,
+void orc_lattice_init(orc_lattice *L, const double *n, const double *T, const double *vx,
                       const double *vy, double *f)
 {
+    free(L->n_prev);  /* the next collision takes the density of f(0) */
+    L->n_prev = NULL;
     const size_t plane = (size_t)L->nx * L->ny;
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < L->ny; ++y) {
