@@ -136,6 +136,100 @@ def copy_calibration(nbytes: int, reps: int = 20):
             "ms_per_copy": round(ms, 4)}
 
 
+WEIGHTS = os.path.join(HERE, "paper_1804_02418_amd", "data", "unet_graphene256.npz")
+
+
+def precision_report(nx: int = 4096, ny: int = 2048, steps: int = 20000, block: int = 8):
+    """Run the graphene sample in FP64, FP32 and FP16-deviation storage for
+    `steps` steps and report the max-relative errors of FP32 and FP16 against
+    FP64 on the block-mean downsample (8 x 8 blocks: 512 x 256 at 4096 x
+    2048), and on the full fields.  The FP64 path is the reference: it is held
+    to the FP64 oracle at 1e-12 by the parity tests."""
+    import numpy as np
+    import torch
+
+    from paper_1804_02418_amd import workloads
+
+    w = workloads.graphene_sample(nx, ny)
+
+    def down(a):
+        return a.reshape(ny // block, block, nx // block, block).mean(axis=(1, 3))
+
+    fields, times = {}, {}
+    for st in ("f64", "f32", "f16dev"):
+        stream = torch.cuda.current_stream()
+        L = make_lattice(w, st, stream.cuda_stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.step(steps)
+        f = L.read_fields()
+        times[st] = time.perf_counter() - t0
+        fields[st] = f
+        L.close()
+    ref = fields["f64"]
+    out = {"workload": w["name"], "steps": steps, "downsample": [ny // block, nx // block],
+           "seconds": {k: round(v, 2) for k, v in times.items()}}
+    for st in ("f32", "f16dev"):
+        g = fields[st]
+        rep = {}
+        for tag, fn in (("downsampled", down), ("full", lambda a: a)):
+            rn, gn = fn(ref["n"]), fn(g["n"])
+            ru = np.hypot(fn(ref["vx"]), fn(ref["vy"]))
+            du = np.hypot(fn(g["vx"]) - fn(ref["vx"]), fn(g["vy"]) - fn(ref["vy"]))
+            rep[tag] = {"err_n": float(np.max(np.abs(gn - rn) / np.abs(rn))),
+                        "err_u": float(du.max() / ru.max()), "max_u": float(ru.max())}
+        out[st] = rep
+    return out
+
+
+def main_precision(argv):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--nx", type=int, default=4096)
+    ap.add_argument("--ny", type=int, default=2048)
+    ap.add_argument("--steps", type=int, default=20000)
+    a = ap.parse_args(argv)
+    print(json.dumps(precision_report(a.nx, a.ny, a.steps)), flush=True)
+    return 0
+
+
+def warm_vs_cold(path: str, count: int = 16, first_index: int = 6000, tol: float = 1e-8,
+                 max_steps: int = 400_000):
+    """Time to a 1e-8 residual of `count` held-out 256 x 256 samples (seeds
+    disjoint from the training set), started cold (uniform equilibrium) and
+    warm (the trained surrogate's prediction), each as one batched FP64 run.
+    Warm wall time includes the network's inference."""
+    import numpy as np
+    import torch
+
+    from paper_1804_02418_amd import _binding as B
+    from paper_1804_02418_amd import surrogate as S
+    from paper_1804_02418_amd import workloads
+
+    d = np.load(path)
+    size = int(d["size"])
+    held = workloads.batch_samples(first_index + count, fixed_size=(size, size))[first_index:]
+    net = B.UNet(int(d["base"]), int(d["cin"]), int(d["cout"]), size, size, max_batch=8)
+    net.set_params(d["theta"])
+    X = np.stack([S.encode(w) for w in held])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    preds = S.predict(net, X, 8) * d["scale"]
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    inits = S.warm_start_inits(held, preds)
+    _, steps_w, r_w, t_w = S.solve_batch(held, max_steps, tol=tol, init=inits)
+    _, steps_c, r_c, t_c = S.solve_batch(held, max_steps, tol=tol)
+    net.close()
+    return {"samples": count, "size": size, "tol": tol,
+            "cold": {"steps_median": float(np.median(steps_c)), "steps_mean": float(np.mean(steps_c)),
+                     "seconds": round(t_c, 3), "converged": int((r_c < tol).sum())},
+            "warm": {"steps_median": float(np.median(steps_w)), "steps_mean": float(np.mean(steps_w)),
+                     "seconds_incl_inference": round(t_w + t_inf, 3), "inference_seconds": round(t_inf, 4),
+                     "converged": int((r_w < tol).sum()),
+                     "fallbacks": sum(1 for i in inits if i is None)},
+            "speedup_wall": round(t_c / (t_w + t_inf), 3)}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,7 +238,8 @@ def main(argv=None):
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16dev"])
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--ny", type=int, default=512)
-    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps for the CPU baseline (0 = skip)")
+    ap.add_argument("--cpu-steps", type=int, default=200, help="oracle steps for the CPU baseline (0 = skip)")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the surrogate warm- vs cold-start timing")
     ap.add_argument("--variants", action="store_true", help="also time the other storages and 4096x2048")
     ap.add_argument("--copy-bytes", type=int, default=0, help="only run the copy-bandwidth calibration")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch shape")
@@ -198,6 +293,8 @@ def main(argv=None):
             s3, l3, _ = run_gpu(big, st, 200, 20)
             extra[f"{big['name']}_{st}"] = round(4096 * 2048 * 200 / s3 / 1e6, 1)
         out["variants_mlups"] = extra
+    if not args.no_warm_start and os.path.exists(WEIGHTS):
+        out["time_to_steady"] = warm_vs_cold(WEIGHTS)
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)
@@ -205,4 +302,6 @@ def main(argv=None):
 
 
 if __name__ == "__main__":
+    if len(sys.argv) > 1 and sys.argv[1] == "--precision-report":
+        sys.exit(main_precision(sys.argv[2:]))
     sys.exit(main())
