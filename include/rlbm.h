@@ -131,6 +131,19 @@ rlbm_status rlbm_set_tau(rlbm_lattice *lat, double tau);
  * (Sec. 2.4 forcing scheme; the electrostatic drive of Sec. 3 held uniform). */
 rlbm_status rlbm_set_drive(rlbm_lattice *lat, double Fx, double Fy);
 
+/* Local-capacitance electrostatics (Sec. 3, Eq. lca): the potential
+ * phi = -e n / C_g adds the per-particle force -(e^2 / C_g) grad n (carriers
+ * repel; e = 1 in lattice units) to the drive: F = (Fx, Fy) - inv_cg grad n.
+ * grad n is the central difference of the density of the previous state (of
+ * f(0) itself for the first collision); a neighbour off the lattice (no
+ * periodic wrap) or solid takes the site's own density.  inv_cg = 1/C_g must
+ * be finite and >= 0 (RLBM_EINVAL otherwise); 0 switches the term off
+ * (C_g = infinity).  Best set before rlbm_init_*; switched on later, the
+ * previous density is taken from the current fields (RLBM_ESTATE if there
+ * are none).  Costs one extra 8-byte density read and write per site and
+ * step.  Lattices with the term on cannot be stepped in a batch. */
+rlbm_status rlbm_set_lca(rlbm_lattice *lat, double inv_cg);
+
 /* Reference state of the deviation storage: f_ref_i = f^eq_i(n_ref, T_ref, 0)
  * and the stored value is (f_i - f_ref_i) / (w_i * scale).  Must be called
  * before rlbm_init_*; n_ref > 0, T_ref > 0, scale > 0. */
@@ -177,9 +190,11 @@ rlbm_status rlbm_step_until(rlbm_lattice *lat, int64_t max_steps, int64_t check_
 rlbm_status rlbm_read_populations(rlbm_lattice *lat, double *f, int on_device);
 
 /* Checkpoint: size of, copy out and restore the whole state (a header, the
- * raw population storage and the fields).  rlbm_set_state requires a lattice
- * created with the same nx, ny and storage; continuing from a restored state
- * is bit-identical to continuing from the saved one.  Host buffers. */
+ * raw population storage, the fields and, with the local-capacitance force
+ * on, the previous density).  rlbm_set_state requires a lattice created with
+ * the same nx, ny and storage and with the force on or off as when saved
+ * (RLBM_EINVAL otherwise); continuing from a restored state is bit-identical
+ * to continuing from the saved one.  Host buffers. */
 rlbm_status rlbm_state_bytes(rlbm_lattice *lat, size_t *bytes);
 rlbm_status rlbm_get_state(rlbm_lattice *lat, void *dst, size_t bytes);
 rlbm_status rlbm_set_state(rlbm_lattice *lat, const void *src, size_t bytes);

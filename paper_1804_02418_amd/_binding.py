@@ -63,6 +63,7 @@ SIGNATURES = {
     "rlbm_set_mask": ([_vp, _vp], None),
     "rlbm_set_tau": ([_vp, ctypes.c_double], None),
     "rlbm_set_drive": ([_vp, ctypes.c_double, ctypes.c_double], None),
+    "rlbm_set_lca": ([_vp, ctypes.c_double], None),
     "rlbm_set_reference": ([_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double], None),
     "rlbm_init_uniform": ([_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double], None),
     "rlbm_init_fields": ([_vp, _vp, _vp, _vp, _vp, ctypes.c_int], None),
@@ -207,6 +208,11 @@ class Lattice:
 
     def set_drive(self, Fx, Fy=0.0):
         check(lib().rlbm_set_drive(self._h, float(Fx), float(Fy)))
+
+    def set_lca(self, cg):
+        """Local-capacitance force with capacitance C_g (None or inf: off)."""
+        inv = 0.0 if cg is None or not np.isfinite(cg) else 1.0 / float(cg)
+        check(lib().rlbm_set_lca(self._h, inv))
 
     def set_reference(self, n_ref=1.0, T_ref=1.0, scale=1.0):
         check(lib().rlbm_set_reference(self._h, float(n_ref), float(T_ref), float(scale)))

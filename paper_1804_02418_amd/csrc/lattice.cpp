@@ -134,6 +134,11 @@ struct rlbm_lattice {
     int part_blocks = 0;
     double *fref = nullptr, *wscale = nullptr;
     unsigned *gtab = nullptr;  // boundary gather table
+    // local-capacitance force: 1/C_g (0: off) and the density ping-pong,
+    // nlca[ncur] holding the density of the current state
+    double inv_cg = 0.0;
+    double *nlca[2] = {nullptr, nullptr};
+    int ncur = 0;
     long long gtab_rows = 0;
     // argument blocks (one is used, by storage)
     StepArgs<double> args_d{};
@@ -183,6 +188,17 @@ void fill_args(rlbm_lattice *L, StepArgs<R> &A)
     A.fvx = L->fld + L->plane();
     A.fvy = L->fld + 2 * L->plane();
     A.feps = L->fld + 3 * L->plane();
+    A.inv_cg = L->inv_cg;
+    A.n_prev = L->inv_cg != 0.0 ? L->nlca[L->ncur] : nullptr;
+    A.n_next = L->inv_cg != 0.0 ? L->nlca[L->ncur ^ 1] : nullptr;
+}
+
+// Point the local-capacitance density buffers of both argument blocks at
+// (n_prev, n_next).
+void set_lca_buffers(rlbm_lattice *L, const double *n_prev, double *n_next)
+{
+    L->args_d.n_prev = L->args_f.n_prev = n_prev;
+    L->args_d.n_next = L->args_f.n_next = n_next;
 }
 
 // Boundary rules of the pull (periodic wrap, then contact span, then
@@ -392,6 +408,8 @@ void rlbm_destroy(rlbm_lattice *L)
     dfree(L->fref);
     dfree(L->wscale);
     dfree(L->gtab);
+    dfree(L->nlca[0]);
+    dfree(L->nlca[1]);
     delete L;
 }
 
@@ -529,6 +547,27 @@ rlbm_status rlbm_set_drive(rlbm_lattice *L, double Fx, double Fy)
     return refresh(L, false);
 }
 
+rlbm_status rlbm_set_lca(rlbm_lattice *L, double inv_cg)
+{
+    CHECK_L(L);
+    if (!std::isfinite(inv_cg) || inv_cg < 0.0)
+        return fail(RLBM_EINVAL, "rlbm_set_lca: 1/C_g must be finite and >= 0 (got %g)", inv_cg);
+    if (inv_cg != 0.0 && !L->nlca[0]) {
+        const size_t b = (size_t)L->plane() * sizeof(double);
+        HIP_TRY(hipMalloc((void **)&L->nlca[0], b));
+        HIP_TRY(hipMalloc((void **)&L->nlca[1], b));
+    }
+    if (inv_cg != 0.0 && L->inv_cg == 0.0 && L->initialized) {
+        // switched on mid-run: the previous density is that of the current state
+        if (!L->fields_valid) return fail(RLBM_ESTATE, "rlbm_set_lca: the current state has no fields");
+        L->ncur = 0;
+        HIP_TRY(hipMemcpyAsync(L->nlca[0], L->fld, (size_t)L->plane() * sizeof(double), hipMemcpyDeviceToDevice,
+                               L->stream));
+    }
+    L->inv_cg = inv_cg;
+    return refresh(L, false);
+}
+
 rlbm_status rlbm_set_reference(rlbm_lattice *L, double n_ref, double T_ref, double scale)
 {
     CHECK_L(L);
@@ -546,7 +585,16 @@ static rlbm_status do_init(rlbm_lattice *L, const double *n, const double *T, co
                            const double u[4])
 {
     L->cur = 0;
-    HIP_TRY(launch_init(L->store(), L->args(), n, T, vx, vy, u, L->pop[0], L->stream));
+    if (L->inv_cg != 0.0) {
+        // the collision of f(0) takes grad n of f(0) itself: its density first
+        L->ncur = 0;
+        set_lca_buffers(L, nullptr, L->nlca[0]);
+        HIP_TRY(launch_init(L->store(), L->args(), n, T, vx, vy, u, L->pop[0], kInitDensity, L->stream));
+        set_lca_buffers(L, L->nlca[0], L->nlca[1]);
+        HIP_TRY(launch_init(L->store(), L->args(), n, T, vx, vy, u, L->pop[0], kInitLca, L->stream));
+    } else {
+        HIP_TRY(launch_init(L->store(), L->args(), n, T, vx, vy, u, L->pop[0], kInitPlain, L->stream));
+    }
     // the state after init holds f*(0); its fields are those of f(0)
     HIP_TRY(hipMemcpyAsync(L->prev, L->fld + L->plane(), 2 * L->plane() * sizeof(double), hipMemcpyDeviceToDevice,
                            L->stream));
@@ -593,10 +641,13 @@ rlbm_status rlbm_step(rlbm_lattice *L, int64_t nsteps)
     if (nsteps == 0) return RLBM_OK;
     HIP_TRY(hipMemcpyAsync(L->prev, L->fld + L->plane(), 2 * L->plane() * sizeof(double), hipMemcpyDeviceToDevice,
                            L->stream));
+    const bool lca = L->inv_cg != 0.0;
     for (int64_t k = 0; k < nsteps; ++k) {
         set_write_fields(L, k == nsteps - 1);
+        if (lca) set_lca_buffers(L, L->nlca[L->ncur], L->nlca[L->ncur ^ 1]);
         HIP_TRY(launch_step(L->store(), L->args(), L->pop[L->cur], L->pop[1 - L->cur], L->shape, L->stream));
         L->cur ^= 1;
+        if (lca) L->ncur ^= 1;
     }
     set_write_fields(L, 0);
     L->t += nsteps;
@@ -709,7 +760,7 @@ struct StateHeader {
     int32_t version, nx, ny, storage;
     int64_t t, last_K;
     double n_ref, T_ref, scale;
-    int32_t fields_valid, pad;
+    int32_t fields_valid, lca;  // lca: the density of the current state follows the fields
 };
 constexpr uint64_t kMagic = 0x524c424d53544154ull;  // "RLBMSTAT"
 }  // namespace
@@ -719,7 +770,7 @@ rlbm_status rlbm_state_bytes(rlbm_lattice *L, size_t *bytes)
     CHECK_L(L);
     if (!bytes) return fail(RLBM_EINVAL, "rlbm_state_bytes: NULL");
     const size_t P = (size_t)L->plane();
-    *bytes = sizeof(StateHeader) + P * kQ * store_bytes(L->storage) + 6 * P * sizeof(double);
+    *bytes = sizeof(StateHeader) + P * kQ * store_bytes(L->storage) + (L->inv_cg != 0.0 ? 7 : 6) * P * sizeof(double);
     return RLBM_OK;
 }
 
@@ -731,8 +782,9 @@ rlbm_status rlbm_get_state(rlbm_lattice *L, void *dst, size_t bytes)
     if (!dst || bytes < need) return fail(RLBM_EINVAL, "rlbm_get_state: buffer too small (%zu < %zu)", bytes, need);
     if (!L->initialized) return fail(RLBM_ESTATE, "rlbm_get_state: not initialised");
     const size_t P = (size_t)L->plane();
+    const int lca = L->inv_cg != 0.0 ? 1 : 0;
     StateHeader h{kMagic, 1, L->nx, L->ny, (int32_t)L->storage, L->t, L->last_K, L->n_ref, L->T_ref, L->scale,
-                  L->fields_valid ? 1 : 0, 0};
+                  L->fields_valid ? 1 : 0, lca};
     char *p = static_cast<char *>(dst);
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
@@ -742,6 +794,8 @@ rlbm_status rlbm_get_state(rlbm_lattice *L, void *dst, size_t bytes)
     HIP_TRY(hipMemcpyAsync(p, L->fld, 4 * P * sizeof(double), hipMemcpyDeviceToHost, L->stream));
     p += 4 * P * sizeof(double);
     HIP_TRY(hipMemcpyAsync(p, L->prev, 2 * P * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    p += 2 * P * sizeof(double);
+    if (lca) HIP_TRY(hipMemcpyAsync(p, L->nlca[L->ncur], P * sizeof(double), hipMemcpyDeviceToHost, L->stream));
     HIP_TRY(hipStreamSynchronize(L->stream));
     return RLBM_OK;
 }
@@ -756,6 +810,9 @@ rlbm_status rlbm_set_state(rlbm_lattice *L, const void *src, size_t bytes)
     std::memcpy(&h, src, sizeof h);
     if (h.magic != kMagic || h.version != 1 || h.nx != L->nx || h.ny != L->ny || h.storage != (int32_t)L->storage)
         return fail(RLBM_EINVAL, "rlbm_set_state: state does not match this lattice");
+    if (h.lca != (L->inv_cg != 0.0 ? 1 : 0))
+        return fail(RLBM_EINVAL, "rlbm_set_state: the state was saved with the local-capacitance force %s",
+                    h.lca ? "on" : "off");
     if (h.n_ref != L->n_ref || h.T_ref != L->T_ref || h.scale != L->scale) {
         L->n_ref = h.n_ref;
         L->T_ref = h.T_ref;
@@ -772,6 +829,11 @@ rlbm_status rlbm_set_state(rlbm_lattice *L, const void *src, size_t bytes)
     HIP_TRY(hipMemcpyAsync(L->fld, p, 4 * P * sizeof(double), hipMemcpyHostToDevice, L->stream));
     p += 4 * P * sizeof(double);
     HIP_TRY(hipMemcpyAsync(L->prev, p, 2 * P * sizeof(double), hipMemcpyHostToDevice, L->stream));
+    p += 2 * P * sizeof(double);
+    if (h.lca) {
+        L->ncur = 0;
+        HIP_TRY(hipMemcpyAsync(L->nlca[0], p, P * sizeof(double), hipMemcpyHostToDevice, L->stream));
+    }
     HIP_TRY(hipStreamSynchronize(L->stream));
     L->t = h.t;
     L->last_K = h.last_K;
@@ -798,9 +860,10 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
     const size_t pb = P * kQ * store_bytes(L->storage);
     // save the state (current populations, fields, previous velocities)
     void *save = nullptr;
-    HIP_TRY(hipMalloc(&save, pb + 6 * P * sizeof(double)));
+    HIP_TRY(hipMalloc(&save, pb + 7 * P * sizeof(double)));
     char *sv = static_cast<char *>(save);
-    const int cur0 = L->cur;
+    const int cur0 = L->cur, ncur0 = L->ncur;
+    const bool lca = L->inv_cg != 0.0;
     const int64_t t0 = L->t, k0 = L->last_K;
     const bool fv0 = L->fields_valid;
     const LaunchShape shape0 = L->shape;
@@ -809,6 +872,9 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
     if (e == hipSuccess)
         e = hipMemcpyAsync(sv + pb + 4 * P * sizeof(double), L->prev, 2 * P * sizeof(double), hipMemcpyDeviceToDevice,
                            L->stream);
+    if (e == hipSuccess && lca)
+        e = hipMemcpyAsync(sv + pb + 6 * P * sizeof(double), L->nlca[ncur0], P * sizeof(double),
+                           hipMemcpyDeviceToDevice, L->stream);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (e == hipSuccess) e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -849,6 +915,10 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
     if (e == hipSuccess)
         e = hipMemcpyAsync(L->prev, sv + pb + 4 * P * sizeof(double), 2 * P * sizeof(double), hipMemcpyDeviceToDevice,
                            L->stream);
+    L->ncur = ncur0;
+    if (e == hipSuccess && lca)
+        e = hipMemcpyAsync(L->nlca[ncur0], sv + pb + 6 * P * sizeof(double), P * sizeof(double),
+                           hipMemcpyDeviceToDevice, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     dfree(save);
     if (e0) (void)hipEventDestroy(e0);
@@ -1111,6 +1181,9 @@ rlbm_status rlbm_batch_step(rlbm_batch *B, int64_t nsteps, int use_graph)
     if (!B) return fail(RLBM_EINVAL, "rlbm_batch_step: NULL batch");
     if (nsteps < 0) return fail(RLBM_EINVAL, "rlbm_batch_step: negative step count");
     if (nsteps == 0) return RLBM_OK;
+    for (size_t s = 0; s < B->lat.size(); ++s)
+        if (B->active[s] && B->lat[s]->inv_cg != 0.0)
+            return fail(RLBM_EINVAL, "rlbm_batch_step: sample %zu has the local-capacitance force on (step it alone)", s);
     // descriptors reflect each sample's current buffer, shape and parameters
     rlbm_status st = upload_descs(B);
     if (st) return st;

@@ -131,6 +131,13 @@ struct StepArgs {
     long long nbnd;
     // fields (float64 SoA), written when write_fields != 0
     double *fn, *fvx, *fvy, *feps;
+    // local-capacitance force F = drive - inv_cg * grad n (Sec. 3, Eq. lca):
+    // n_prev holds the density of the previous state (central differences,
+    // an off-lattice or solid neighbour taking the site's own density);
+    // every step writes its own density to n_next.  n_prev == null: off.
+    double inv_cg;
+    const double *n_prev;
+    double *n_next;
 };
 
 enum class Store { F64 = 0, F32 = 1, F16 = 2 };
@@ -170,9 +177,13 @@ hipError_t launch_batch_residual(Store st, const void *descs, int nsamples, int 
                                  hipStream_t s);
 
 // Initial post-collision state from fields (n, T, vx, vy; null pointers ->
-// the uniform values u[4]).  Writes dst and the fields of the initial state.
+// the uniform values u[4]).  mode kInitPlain: writes dst and the fields of
+// the initial state; kInitDensity: writes only the density of f(0) to
+// n_next; kInitLca: as plain, the collision taking the local-capacitance
+// force from n_prev (the density written by a kInitDensity pass).
+enum InitMode { kInitPlain = 0, kInitDensity = 1, kInitLca = 2 };
 hipError_t launch_init(Store st, const void *args, const double *n, const double *T, const double *vx,
-                       const double *vy, const double u[4], void *dst, hipStream_t s);
+                       const double *vy, const double u[4], void *dst, int mode, hipStream_t s);
 
 // Decode storage to float64 populations f_i = f_ref_i + w_i * scale * eta_i.
 hipError_t launch_decode(Store st, int nx, int ny, const void *src, const double *fref, const double *wscale,

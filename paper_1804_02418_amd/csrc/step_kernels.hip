@@ -56,7 +56,8 @@ struct SiteFields {
 // equilibrium and forcing polynomials -> relaxation with
 // omega_d = p_i.U / (p0_i tau) = (U^0 - nhat_d . U_s) / tau.
 template <class R>
-__device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, SiteFields &out)
+__device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, SiteFields &out, R fx, R fy,
+                                             bool has_force)
 {
     // ---- moments of the deviation, one pair of opposite directions at a time ----
     R N0 = 0, Nx = 0, Ny = 0, T00 = 0, T0x = 0, T0y = 0, Txx = 0, Txy = 0, Tyy = 0;
@@ -104,7 +105,7 @@ __device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, S
     for (int k = 0; k < kK; ++k) ad[k] = R((a[k] - A.a_ref[k]) * A.inv_scale);
     R Ha[kK], Hb[kK];
     appendix_a_to_harmonics(ad, Ha);
-    if (A.has_force) {
+    if (has_force) {
         // b = (Fx C_x + Fy C_y) a / scale with a / scale = ad + a_ref / scale
         R as[kK];
 #pragma unroll
@@ -114,16 +115,16 @@ __device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, S
         R bx[kK], by[kK], b[kK];
 #pragma unroll
         for (int k = 0; k < kK; ++k) bx[k] = by[k] = R(0);
-        if (A.fx != R(0)) {
+        if (fx != R(0)) {
 #pragma unroll
             for (int q = 0; q < kForceNx; ++q) bx[kForceX[q].k] += R(kForceX[q].v) * as[kForceX[q].m];
         }
-        if (A.fy != R(0)) {
+        if (fy != R(0)) {
 #pragma unroll
             for (int q = 0; q < kForceNy; ++q) by[kForceY[q].k] += R(kForceY[q].v) * as[kForceY[q].m];
         }
 #pragma unroll
-        for (int k = 0; k < kK; ++k) b[k] = A.fx * bx[k] + A.fy * by[k];
+        for (int k = 0; k < kK; ++k) b[k] = fx * bx[k] + fy * by[k];
         appendix_a_to_harmonics(b, Hb);
     } else {
 #pragma unroll
@@ -171,6 +172,44 @@ __device__ __forceinline__ void write_fields(const StepArgs<R> &A, long long sit
     A.fvx[site] = f.vx;
     A.fvy[site] = f.vy;
     A.feps[site] = f.eps;
+}
+
+// Density of the previous state at (x, y) for the local-capacitance gradient
+// at (x0, y0): periodic wrap, else an off-lattice or solid neighbour takes
+// the density of the site itself.
+template <class R>
+__device__ __forceinline__ double lca_density(const StepArgs<R> &A, int x, int y, long long site0)
+{
+    if (A.periodic_x) x = x < 0 ? x + A.nx : (x >= A.nx ? x - A.nx : x);
+    if (A.periodic_y) y = y < 0 ? y + A.ny : (y >= A.ny ? y - A.ny : y);
+    if ((unsigned)x >= (unsigned)A.nx || (unsigned)y >= (unsigned)A.ny) return A.n_prev[site0];
+    const long long s = (long long)y * A.nx + x;
+    if (A.has_mask && A.mask[s]) return A.n_prev[site0];
+    return A.n_prev[s];
+}
+
+// Total force on a site with the local-capacitance term: drive minus
+// inv_cg times the central-difference gradient of the previous density.
+// `inner`: the four neighbours lie on the lattice and none is solid.
+template <class R>
+__device__ __forceinline__ void lca_force(const StepArgs<R> &A, int x, int y, long long site, bool inner, R &fx,
+                                          R &fy)
+{
+    double ge, gw, gn, gs;
+    if (inner) {
+        ge = A.n_prev[site + 1];
+        gw = A.n_prev[site - 1];
+        gn = A.n_prev[site + A.nx];
+        gs = A.n_prev[site - A.nx];
+    } else {
+        ge = lca_density(A, x + 1, y, site);
+        gw = lca_density(A, x - 1, y, site);
+        gn = lca_density(A, x, y + 1, site);
+        gs = lca_density(A, x, y - 1, site);
+    }
+    const double gx = 0.5 * (ge - gw), gy = 0.5 * (gn - gs);
+    fx = R(double(A.fx) - A.inv_cg * gx);
+    fy = R(double(A.fy) - A.inv_cg * gy);
 }
 
 // Gather of one site with the boundary rules: periodic wrap, then a contact's
@@ -224,7 +263,7 @@ __device__ __forceinline__ void gather_general(const StepArgs<R> &A, const S *__
 // gather), the rest tile the interior x in [5, nx - 5), y in [5, ny - 5)
 // with tile_x * rows sites per block, tiles aligned to tile_x so every
 // wavefront stores 64 aligned values.
-template <class S, class R>
+template <class S, class R, bool LCA>
 __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__restrict__ src, S *__restrict__ dst,
                                            int b, int nbnd, int tile_x, int tiles_x, int all, int wf)
 {
@@ -232,11 +271,13 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
     const int nx = A.nx;
     const long long P = A.plane;
     int x, y;
+    bool inner;
     R h[kQ];
     if (b < nbnd) {
         const long long idx = (long long)b * blockDim.x + t;
         if (idx >= boundary_count(nx, A.ny, all)) return;
         boundary_site(idx, nx, A.ny, all, x, y);
+        inner = false;
         const long long site = (long long)y * nx + x;
         if (A.has_mask && A.mask[site]) {
             if (wf) {
@@ -266,6 +307,7 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
         x = bx * tile_x + (t - ty * tile_x);
         y = kReach + by * rows + ty;
         if (x < kReach || x >= nx - kReach || y >= A.ny - kReach) return;
+        inner = true;
         // uniform plane base pointers + one 32-bit site offset
         const unsigned site = (unsigned)y * (unsigned)nx + (unsigned)x;
 #pragma unroll
@@ -277,7 +319,16 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
     }
     const unsigned site = (unsigned)y * (unsigned)nx + (unsigned)x;
     SiteFields f;
-    const bool ok = collide_site<R>(h, A, f);
+    bool ok;
+    if constexpr (LCA) {
+        R fx, fy;
+        lca_force(A, x, y, site, inner, fx, fy);
+        ok = collide_site<R>(h, A, f, fx, fy, true);
+        A.n_next[site] = ok ? f.n : NAN;
+    } else {
+        (void)inner;
+        ok = collide_site<R>(h, A, f, A.fx, A.fy, A.has_force != 0);
+    }
     if (wf) write_fields(A, site, f, ok);
     if (A.nt_store) {
         // streaming stores: the next step reads these values once, from HBM
@@ -292,11 +343,11 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
     }
 }
 
-template <class S, class R>
+template <class S, class R, bool LCA>
 __global__ __launch_bounds__(256) void step_kernel(const StepArgs<R> A, const S *__restrict__ src,
                                                    S *__restrict__ dst, int nbnd, int tile_x, int tiles_x, int all)
 {
-    step_block<S, R>(A, src, dst, blockIdx.x, nbnd, tile_x, tiles_x, all, A.write_fields);
+    step_block<S, R, LCA>(A, src, dst, blockIdx.x, nbnd, tile_x, tiles_x, all, A.write_fields);
 }
 
 // Batched step: a persistent grid drains the work list of (sample, block)
@@ -321,8 +372,8 @@ __global__ __launch_bounds__(256) void batch_step_kernel(const BatchDesc<R> *__r
         const int smp = (int)(it >> kItemBlockBits), b = (int)(it & ((1u << kItemBlockBits) - 1));
         const BatchDesc<R> &D = descs[smp];
         const int par = parity ^ D.parity_xor;
-        step_block<S, R>(D.a, static_cast<const S *>(D.pop[par]), static_cast<S *>(D.pop[par ^ 1]), b, D.nbnd, D.tile_x,
-                         D.tiles_x, D.all, wf);
+        step_block<S, R, false>(D.a, static_cast<const S *>(D.pop[par]), static_cast<S *>(D.pop[par ^ 1]), b, D.nbnd,
+                                D.tile_x, D.tiles_x, D.all, wf);
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -385,11 +436,12 @@ template <class S, class R>
 __global__ __launch_bounds__(256) void init_kernel(const StepArgs<R> A, const double *__restrict__ n_in,
                                                    const double *__restrict__ T_in, const double *__restrict__ vx_in,
                                                    const double *__restrict__ vy_in, double un, double uT, double uvx,
-                                                   double uvy, S *__restrict__ dst)
+                                                   double uvy, S *__restrict__ dst, int mode)
 {
     const long long site = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (site >= A.plane) return;
     if (A.has_mask && A.mask[site]) {
+        if (mode == kInitDensity) return;
         for (int i = 0; i < kQ; ++i) StoreIO<S>::template store<R>(dst + (long long)i * A.plane + site, R(0));
         A.fn[site] = 0.0;
         A.fvx[site] = 0.0;
@@ -420,7 +472,18 @@ __global__ __launch_bounds__(256) void init_kernel(const StepArgs<R> A, const do
         }
     }
     SiteFields f;
-    const bool ok = collide_site<R>(h, A, f);
+    R fx = A.fx, fy = A.fy;
+    bool force = A.has_force != 0;
+    if (mode == kInitLca) {
+        const int y = (int)(site / A.nx), x = (int)(site - (long long)y * A.nx);
+        lca_force(A, x, y, site, false, fx, fy);
+        force = true;
+    }
+    const bool ok = collide_site<R>(h, A, f, fx, fy, force);
+    if (mode == kInitDensity) {
+        A.n_next[site] = ok ? f.n : NAN;
+        return;
+    }
     write_fields(A, site, f, ok);
     for (int i = 0; i < kQ; ++i) StoreIO<S>::template store<R>(dst + (long long)i * A.plane + site, h[i]);
 }
@@ -494,20 +557,28 @@ hipError_t launch_step_t(const void *args, const void *src, void *dst, LaunchSha
         tiles_x = (A.nx + sh.tile_x - 1) / sh.tile_x;
         tiles = tiles_x * ((A.ny - 2 * kReach + rows - 1) / rows);
     }
-    hipLaunchKernelGGL((step_kernel<S, R>), dim3((unsigned)(nbnd + tiles)), dim3(block), 0, s, A,
-                       static_cast<const S *>(src), static_cast<S *>(dst), nbnd, sh.tile_x, tiles_x, interior ? 0 : 1);
+    if (A.n_prev)
+        hipLaunchKernelGGL((step_kernel<S, R, true>), dim3((unsigned)(nbnd + tiles)), dim3(block), 0, s, A,
+                           static_cast<const S *>(src), static_cast<S *>(dst), nbnd, sh.tile_x, tiles_x,
+                           interior ? 0 : 1);
+    else
+        hipLaunchKernelGGL((step_kernel<S, R, false>), dim3((unsigned)(nbnd + tiles)), dim3(block), 0, s, A,
+                           static_cast<const S *>(src), static_cast<S *>(dst), nbnd, sh.tile_x, tiles_x,
+                           interior ? 0 : 1);
     return hipGetLastError();
 }
 
 template <class S, class R>
 hipError_t launch_init_t(const void *args, const double *n, const double *T, const double *vx, const double *vy,
-                         const double u[4], void *dst, hipStream_t s)
+                         const double u[4], void *dst, int mode, hipStream_t s)
 {
     const StepArgs<R> &A = *static_cast<const StepArgs<R> *>(args);
+    if ((mode == kInitDensity && !A.n_next) || (mode == kInitLca && !A.n_prev) || mode < 0 || mode > 2)
+        return hipErrorInvalidValue;
     const int block = 256;
     const long long grid = (A.plane + block - 1) / block;
     hipLaunchKernelGGL((init_kernel<S, R>), dim3((unsigned)grid), dim3(block), 0, s, A, n, T, vx, vy, u[0], u[1], u[2],
-                       u[3], static_cast<S *>(dst));
+                       u[3], static_cast<S *>(dst), mode);
     return hipGetLastError();
 }
 
@@ -580,12 +651,12 @@ hipError_t launch_step(Store st, const void *args, const void *src, void *dst, L
 }
 
 hipError_t launch_init(Store st, const void *args, const double *n, const double *T, const double *vx,
-                       const double *vy, const double u[4], void *dst, hipStream_t s)
+                       const double *vy, const double u[4], void *dst, int mode, hipStream_t s)
 {
     switch (st) {
-    case Store::F64: return launch_init_t<double, double>(args, n, T, vx, vy, u, dst, s);
-    case Store::F32: return launch_init_t<float, float>(args, n, T, vx, vy, u, dst, s);
-    case Store::F16: return launch_init_t<_Float16, float>(args, n, T, vx, vy, u, dst, s);
+    case Store::F64: return launch_init_t<double, double>(args, n, T, vx, vy, u, dst, mode, s);
+    case Store::F32: return launch_init_t<float, float>(args, n, T, vx, vy, u, dst, mode, s);
+    case Store::F16: return launch_init_t<_Float16, float>(args, n, T, vx, vy, u, dst, mode, s);
     }
     return hipErrorInvalidValue;
 }

@@ -10,7 +10,7 @@ def oracle_lattice(w, use_printed=False):
 
     L = oracle.Lattice(oracle.stencil(use_printed), w["nx"], w["ny"], periodic_x=w["periodic_x"],
                        periodic_y=w["periodic_y"], contacts=w["contacts"], solid=w.get("mask"), tau=w["tau"],
-                       F=w["F"])
+                       F=w["F"], cg=w.get("cg"))
     i = w["init"]
     L.init_fields(i["n"], i["T"], i["vx"], i["vy"])
     return L
@@ -25,6 +25,8 @@ def gpu_lattice(w, storage=None, shape=None):
         L.set_mask(w["mask"])
     L.set_tau(w["tau"])
     L.set_drive(*w["F"])
+    if w.get("cg") is not None:
+        L.set_lca(w["cg"])
     i = w["init"]
     if all(np.isscalar(v) for v in i.values()):
         L.init_uniform(i["n"], i["T"], i["vx"], i["vy"])

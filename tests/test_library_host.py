@@ -76,4 +76,5 @@ def test_null_handle_is_rejected():
 
     assert rl.lib().rlbm_set_tau(None, 1.0) == _binding.EINVAL
     assert rl.lib().rlbm_step(None, 1) == _binding.EINVAL
+    assert rl.lib().rlbm_set_lca(None, 0.1) == _binding.EINVAL
     rl.lib().rlbm_destroy(None)
