@@ -207,6 +207,13 @@ rlbm_status rlbm_set_state(rlbm_lattice *lat, const void *src, size_t bytes);
  * to 64. */
 rlbm_status rlbm_set_launch_shape(rlbm_lattice *lat, int tile_x, int rows);
 
+/* Block order of the step kernel: xcd_contiguous = 1 deals each of the 8
+ * XCDs (with its own L2) one contiguous range of the launch's blocks, so
+ * horizontally adjacent tiles, which share cache lines at their edges, run
+ * under one L2; 0 (default) keeps the launch order, in which consecutive
+ * blocks alternate between XCDs.  Results are identical either way. */
+rlbm_status rlbm_set_block_order(rlbm_lattice *lat, int xcd_contiguous);
+
 /* Streaming (non-temporal) stores of the populations: on = 1 makes the step
  * kernel's stores bypass the caches.  Pays off once the two population
  * arrays outgrow the 256 MB Infinity Cache (the default there); below it the
@@ -260,9 +267,11 @@ void rlbm_batch_destroy(rlbm_batch *b);
 rlbm_status rlbm_batch_lattice(rlbm_batch *b, int i, rlbm_lattice **lat);
 
 /* Advance every active sample by nsteps.  Each step is ONE launch of a
- * persistent kernel whose blocks drain the (sample, block) work items of all
- * active samples through an atomic queue; with use_graph the launches are
- * replayed from a captured HIP graph.  Fields are kept for the last step. */
+ * persistent kernel (as many blocks as fit on the device at once) whose
+ * blocks walk the (sample, block) work items of all active samples in a
+ * fixed interleaved order; with use_graph the launches are replayed from a
+ * captured HIP graph.  Fields are kept for the last step.  RLBM_EINVAL if an
+ * active sample has the local-capacitance force on. */
 rlbm_status rlbm_batch_step(rlbm_batch *b, int64_t nsteps, int use_graph);
 
 /* Mark samples active (1) or frozen (0); frozen samples keep their state
@@ -286,6 +295,11 @@ rlbm_status rlbm_batch_step_until(rlbm_batch *b, int64_t max_steps, int64_t chec
  * width), with ordinary and with streaming stores, keep the fastest, restore
  * all states.  ms_per_step: 6 entries or NULL. */
 rlbm_status rlbm_batch_autotune(rlbm_batch *b, int trial_steps, double *ms_per_step);
+
+/* Item order of the batched kernel, as rlbm_set_block_order: 1 deals each
+ * XCD one contiguous range of the items in flight, 0 (default) interleaves
+ * them.  Results are identical either way. */
+rlbm_status rlbm_batch_set_block_order(rlbm_batch *b, int xcd_contiguous);
 
 /* Total lattice sites of the active samples. */
 rlbm_status rlbm_batch_sites(rlbm_batch *b, int64_t *sites);

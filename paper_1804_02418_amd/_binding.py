@@ -64,6 +64,8 @@ SIGNATURES = {
     "rlbm_set_tau": ([_vp, ctypes.c_double], None),
     "rlbm_set_drive": ([_vp, ctypes.c_double, ctypes.c_double], None),
     "rlbm_set_lca": ([_vp, ctypes.c_double], None),
+    "rlbm_set_block_order": ([_vp, ctypes.c_int], None),
+    "rlbm_batch_set_block_order": ([_vp, ctypes.c_int], None),
     "rlbm_set_reference": ([_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double], None),
     "rlbm_init_uniform": ([_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double], None),
     "rlbm_init_fields": ([_vp, _vp, _vp, _vp, _vp, ctypes.c_int], None),
@@ -208,6 +210,9 @@ class Lattice:
 
     def set_drive(self, Fx, Fy=0.0):
         check(lib().rlbm_set_drive(self._h, float(Fx), float(Fy)))
+
+    def set_block_order(self, xcd_contiguous: bool):
+        check(lib().rlbm_set_block_order(self._h, int(bool(xcd_contiguous))))
 
     def set_lca(self, cg):
         """Local-capacitance force with capacitance C_g (None or inf: off)."""
@@ -374,6 +379,9 @@ class Batch:
         ms = np.zeros(6)
         check(lib().rlbm_batch_autotune(self._h, int(trial_steps), ms.ctypes.data_as(_dp)))
         return ms
+
+    def set_block_order(self, xcd_contiguous: bool):
+        check(lib().rlbm_batch_set_block_order(self._h, int(bool(xcd_contiguous))))
 
     def sites(self) -> int:
         n = _i64()

@@ -250,6 +250,41 @@ bool check_harmonic_form(char *err)
     return true;
 }
 
+// The combined relaxation polynomial (omega_harmonics / omega_pair) against
+// omega(t) Qa(t) - Qb(t) evaluated directly, at a direction and its opposite.
+bool check_omega_form(char *err)
+{
+    unsigned s = 54321u;
+    auto rnd = [&s]() {
+        s = s * 1664525u + 1013904223u;
+        return (double)(s >> 8) / 16777216.0 - 0.5;
+    };
+    for (int trial = 0; trial < 64; ++trial) {
+        double Ha[kK], Hb[kK], Wc[4][5], Ws[4][5], E[4], O[4];
+        for (int k = 0; k < kK; ++k) {
+            Ha[k] = rnd();
+            Hb[k] = rnd();
+        }
+        const double U0 = 1.0 + rnd(), Ux = rnd(), Uy = rnd();
+        omega_harmonics(Ha, Hb, U0, Ux, Uy, Wc, Ws);
+        const double t = 6.283185307179586 * rnd(), p0 = 8.0 * (rnd() + 0.5);
+        const DirTrig tg = trig_of(std::cos(t), std::sin(t));
+        omega_pair(Wc, Ws, tg, E, O);
+        for (int side = 0; side < 2; ++side) {
+            const double c = side ? -std::cos(t) : std::cos(t), sn = side ? -std::sin(t) : std::sin(t);
+            const double ref = (U0 - Ux * c - Uy * sn) * harmonics_eval(Ha, p0, c, sn) - harmonics_eval(Hb, p0, c, sn);
+            const double sg = side ? -1.0 : 1.0;
+            const double got = (((E[3] + sg * O[3]) * p0 + (E[2] + sg * O[2])) * p0 + (E[1] + sg * O[1])) * p0 +
+                               (E[0] + sg * O[0]);
+            if (std::fabs(got - ref) > 1e-12 * (1.0 + std::fabs(ref)) * p0 * p0 * p0) {
+                snprintf(err, 256, "combined relaxation polynomial disagrees with its definition (trial %d)", trial);
+                return false;
+            }
+        }
+    }
+    return true;
+}
+
 const Constants &constants()
 {
     static Constants C;
@@ -297,6 +332,7 @@ const Constants &constants()
         }
         if (!force_matrices_exact(C.Cx, C.Cy, C.err)) return;
         if (!check_harmonic_form(C.err)) return;
+        if (!check_omega_form(C.err)) return;
         C.ok = true;
     });
     return C;

@@ -421,6 +421,8 @@ rlbm_status rlbm_create(int nx, int ny, rlbm_storage storage, void *hip_stream, 
         return fail(RLBM_EINVAL, "rlbm_create: invalid size %d x %d", nx, ny);
     if (storage != RLBM_F64 && storage != RLBM_F32 && storage != RLBM_F16DEV)
         return fail(RLBM_EINVAL, "rlbm_create: unknown storage %d", (int)storage);
+    if ((long long)nx * ny * (long long)store_bytes(storage) >= (1LL << 32))
+        return fail(RLBM_EINVAL, "rlbm_create: one population plane of %d x %d exceeds 4 GiB", nx, ny);
     rlbm_lattice *L = new (std::nothrow) rlbm_lattice();
     if (!L) return fail(RLBM_ENOMEM, "rlbm_create: host allocation failed");
     rlbm_status st = load_constants(&L->C);
@@ -847,7 +849,7 @@ rlbm_status rlbm_set_launch_shape(rlbm_lattice *L, int tile_x, int rows)
     CHECK_L(L);
     if (tile_x < 64 || tile_x % 64 || rows < 1 || tile_x * rows != 256)
         return fail(RLBM_EINVAL, "rlbm_set_launch_shape: invalid shape %d x %d", tile_x, rows);
-    L->shape = LaunchShape{tile_x, rows};
+    L->shape = LaunchShape{tile_x, rows, L->shape.xcd};
     return RLBM_OK;
 }
 
@@ -887,7 +889,7 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
         const int tc = c % 3, nt = c / 3;
         if (ms_per_step) ms_per_step[c] = 0.0;
         if (tc > 0 && tiles[tc - 1] >= interior_w) continue;  // wider tiles only add idle lanes
-        L->shape = LaunchShape{tiles[tc], 256 / tiles[tc]};
+        L->shape = LaunchShape{tiles[tc], 256 / tiles[tc], shape0.xcd};
         rlbm_set_streaming_stores(L, nt);
         rlbm_status st = rlbm_step(L, 2);
         if (st == RLBM_OK) e = hipEventRecord(e0, L->stream);
@@ -931,10 +933,18 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
         rlbm_set_streaming_stores(L, nt0);
         return fail(RLBM_EDEVICE, "rlbm_autotune: %s", hipGetErrorString(e));
     }
-    L->shape = LaunchShape{best_tile, 256 / best_tile};
+    L->shape = LaunchShape{best_tile, 256 / best_tile, shape0.xcd};
     rlbm_set_streaming_stores(L, best_nt);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_cache_store(TuneKey(device_arch(), (int)L->storage, L->nx, L->ny, L->mask ? 1 : 0), 2 * best_tile + best_nt);
+    return RLBM_OK;
+}
+
+rlbm_status rlbm_set_block_order(rlbm_lattice *L, int xcd_contiguous)
+{
+    CHECK_L(L);
+    if (xcd_contiguous != 0 && xcd_contiguous != 1) return fail(RLBM_EINVAL, "rlbm_set_block_order: 0 or 1");
+    L->shape.xcd = xcd_contiguous;
     return RLBM_OK;
 }
 
@@ -970,10 +980,9 @@ struct rlbm_batch {
     size_t items_cap = 0;
     int *n_items = nullptr;
     int n_items_host = 0;
-    unsigned *counters = nullptr;
+    int xcd = 0;  // XCD-contiguous item order
     double *part = nullptr;
     int part_blocks = 0;
-    int grid = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     static constexpr int kGraphSteps = 32;
@@ -995,6 +1004,14 @@ int step_blocks(const rlbm_lattice *L, int *nbnd, int *tiles_x, int *all)
         tiles = *tiles_x * ((L->ny - 2 * kReach + rows - 1) / rows);
     }
     return *nbnd + tiles;
+}
+
+void drop_graph(rlbm_batch *B)
+{
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    B->exec = nullptr;
+    B->graph = nullptr;
 }
 
 template <class R>
@@ -1021,6 +1038,8 @@ rlbm_status upload_descs_t(rlbm_batch *B)
     }
     HIP_TRY(hipMemcpyAsync(B->descs, d.data(), n * sizeof(BatchDesc<R>), hipMemcpyHostToDevice, B->stream));
     if (items.size() > B->items_cap) {
+        // the launch grid is the capacity: a captured graph holds the old one
+        drop_graph(B);
         dfree(B->items);
         B->items = nullptr;
         HIP_TRY(hipMalloc((void **)&B->items, items.size() * sizeof(unsigned)));
@@ -1044,8 +1063,8 @@ Store store_of(rlbm_storage st) { return st == RLBM_F64 ? Store::F64 : st == RLB
 
 rlbm_status batch_launch(rlbm_batch *B, int parity, int wf)
 {
-    HIP_TRY(launch_batch_step(store_of(B->storage), B->descs, B->items, B->n_items, B->counters, B->grid, parity, wf,
-                              B->stream));
+    HIP_TRY(launch_batch_step(store_of(B->storage), B->descs, B->items, B->n_items, (int)B->items_cap, parity, wf,
+                              B->xcd, B->stream));
     return RLBM_OK;
 }
 
@@ -1081,7 +1100,6 @@ void rlbm_batch_destroy(rlbm_batch *B)
     dfree(B->descs);
     dfree(B->items);
     dfree(B->n_items);
-    dfree(B->counters);
     dfree(B->part);
     if (B->own_stream && B->stream) (void)hipStreamDestroy(B->stream);
     delete B;
@@ -1134,15 +1152,9 @@ rlbm_status rlbm_batch_create(const rlbm_sample *samples, int nsamples, rlbm_sto
     hipError_t e = hipSuccess;
     if (!st) e = hipMalloc(&B->descs, desc_bytes);
     if (!st && e == hipSuccess) e = hipMalloc((void **)&B->n_items, sizeof(int));
-    if (!st && e == hipSuccess) e = hipMalloc((void **)&B->counters, 2 * sizeof(unsigned));
-    if (!st && e == hipSuccess) e = hipMemsetAsync(B->counters, 0, 2 * sizeof(unsigned), B->stream);
     B->part_blocks = 8;
     if (!st && e == hipSuccess) e = hipMalloc((void **)&B->part, (size_t)nsamples * B->part_blocks * 3 * sizeof(double));
     if (!st && e != hipSuccess) st = fail(RLBM_EDEVICE, "rlbm_batch_create: %s", hipGetErrorString(e));
-    if (!st) {
-        B->grid = batch_resident_blocks(store_of(storage));
-        if (B->grid <= 0) st = fail(RLBM_EDEVICE, "rlbm_batch_create: occupancy query failed");
-    }
     if (!st) st = upload_descs(B);
     if (st) {
         rlbm_batch_destroy(B);
@@ -1156,6 +1168,15 @@ rlbm_status rlbm_batch_lattice(rlbm_batch *B, int i, rlbm_lattice **lat)
 {
     if (!B || !lat || i < 0 || i >= (int)B->lat.size()) return fail(RLBM_EINVAL, "rlbm_batch_lattice: bad argument");
     *lat = B->lat[i];
+    return RLBM_OK;
+}
+
+rlbm_status rlbm_batch_set_block_order(rlbm_batch *B, int xcd_contiguous)
+{
+    if (!B || (xcd_contiguous != 0 && xcd_contiguous != 1))
+        return fail(RLBM_EINVAL, "rlbm_batch_set_block_order: bad argument");
+    if (B->xcd != xcd_contiguous) drop_graph(B);  // the captured graph holds the old order
+    B->xcd = xcd_contiguous;
     return RLBM_OK;
 }
 
@@ -1371,12 +1392,7 @@ rlbm_status rlbm_batch_autotune(rlbm_batch *B, int trial_steps, double *ms_per_s
         if (e != hipSuccess && !st) st = fail(RLBM_EDEVICE, "rlbm_batch_autotune: %s", hipGetErrorString(e));
     }
     dfree(save);
-    if (B->exec) {
-        (void)hipGraphExecDestroy(B->exec);
-        B->exec = nullptr;
-        (void)hipGraphDestroy(B->graph);
-        B->graph = nullptr;
-    }
+    drop_graph(B);
     return st;
 }
 

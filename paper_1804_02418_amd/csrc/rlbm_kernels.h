@@ -158,20 +158,31 @@ struct BatchDesc {
 constexpr int kItemBlockBits = 20;
 
 struct LaunchShape {
-    int tile_x;  // sites per block along x (multiple of 64)
-    int rows;    // rows per block
+    int tile_x;   // sites per block along x (multiple of 64)
+    int rows;     // rows per block
+    int xcd = 0;  // 1: consecutive tiles go to the same XCD (its own L2)
 };
+
+// Workgroups of a launch are dealt to the 8 XCDs in turn (block b runs on
+// XCD b % 8).  With `xcd` on, block b takes logical block xcd_block(b, G) so
+// that each XCD gets one contiguous range of the G logical blocks: tiles
+// that share cache lines (horizontal neighbours) then share an L2.  A
+// bijection of [0, G) for any G.
+__device__ __forceinline__ int xcd_block(int b, int G)
+{
+    const int x = b & 7, q = G >> 3, r = G & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
 
 // One time step src -> dst (post-collision storage, pull streaming): an
 // interior kernel for the sites whose whole stencil lies on the lattice
 // (none when there is a mask) and a boundary kernel for the rest.
 hipError_t launch_step(Store st, const void *args, const void *src, void *dst, LaunchShape shape, hipStream_t s);
 
-// Batched step: `grid` persistent blocks drain *n_items work items.
-hipError_t launch_batch_step(Store st, const void *descs, const unsigned *items, const int *n_items,
-                             unsigned *counters, int grid, int parity, int write_fields, hipStream_t s);
-// Blocks of the batched step kernel that fit on the device at once.
-int batch_resident_blocks(Store st);
+// Batched step: `grid` blocks (at least *n_items), block b taking work item
+// b, or xcd_block(b, grid) when `xcd` is set; blocks past *n_items leave.
+hipError_t launch_batch_step(Store st, const void *descs, const unsigned *items, const int *n_items, int grid,
+                             int parity, int write_fields, int xcd, hipStream_t s);
 // Per-sample residual partial sums (3 doubles per block, blocks_per_sample per sample).
 hipError_t launch_batch_residual(Store st, const void *descs, int nsamples, int blocks_per_sample, double *part,
                                  hipStream_t s);

@@ -42,17 +42,18 @@ constexpr int kCy[kDirs] = {0, 3, 4, 5, 4, 3, 0, -3, -4, -5, -4, -3};
 // 0 for the (+-3,+-4)_FS family (weights w_1j), 1 for (+-5,0)_FS (w_2j).
 constexpr int kGroup[kDirs] = {1, 0, 0, 1, 0, 0, 1, 0, 0, 1, 0, 0};
 
-// Angular constants of the first six directions (the other six are their
-// opposites): cos t, sin t, cos 2t, sin 2t, cos 3t, sin 3t with
-// (cos t, sin t) = n_d / 5.
+// Angular constants of a direction t: cos kt, sin kt for k = 1..4; for the
+// lattice, (cos t, sin t) = n_d / 5 for the first six directions (the other
+// six are their opposites).
 struct DirTrig {
-    double c, s, c2, s2, c3, s3;
+    double c, s, c2, s2, c3, s3, c4, s4;
 };
-RLBM_HD constexpr DirTrig dir_trig(int d)
+RLBM_HD constexpr DirTrig trig_of(double c, double s)
 {
-    const double c = kCx[d] / 5.0, s = kCy[d] / 5.0;
-    return DirTrig{c, s, c * c - s * s, 2.0 * c * s, c * (c * c - 3.0 * s * s), s * (3.0 * c * c - s * s)};
+    return DirTrig{c, s, c * c - s * s, 2.0 * c * s, c * (c * c - 3.0 * s * s), s * (3.0 * c * c - s * s),
+                   (c * c - s * s) * (c * c - s * s) - 4.0 * c * c * s * s, 4.0 * c * s * (c * c - s * s)};
 }
+RLBM_HD constexpr DirTrig dir_trig(int d) { return trig_of(kCx[d] / 5.0, kCy[d] / 5.0); }
 
 // Appendix A (third order, m = 0) in harmonic form: H = sum_k a_k * harm(J_k).
 template <class R>
@@ -112,6 +113,65 @@ RLBM_HD void harmonics_pair(const R H[kK], const DirTrig &tg, R E[4], R O[4])
     O[3] = H[10] * c + H[11] * s + H[14] * c3 + H[15] * s3;
 }
 
+// Relaxation-and-force polynomial in harmonic form.  With
+// omega(t) = U0 - Ux cos t - Uy sin t (the relaxation rate of a direction,
+// times tau), the per-direction update needs omega(t) Qa_e(t) - Qb_e(t) for
+// the radial powers e = 0..3, Qa / Qb having harmonic coefficients Ha / Hb.
+// The product raises the trigonometric degree by one (product-to-sum), so
+// W_e has degree e + 1: cosine coefficients Wc[e][0..e+1], sine
+// coefficients Ws[e][1..e+1] (24 numbers instead of the 32 of Ha and Hb).
+template <class R>
+RLBM_HD void omega_harmonics(const R Ha[kK], const R Hb[kK], R U0, R Ux, R Uy, R Wc[4][5], R Ws[4][5])
+{
+    // harmonic layout of Ha / Hb per power e: cosine and sine coefficients
+    constexpr int kC[4][4] = {{0, -1, -1, -1}, {1, 2, -1, -1}, {4, 5, 7, -1}, {9, 10, 12, 14}};
+    constexpr int kS[4][4] = {{-1, -1, -1, -1}, {-1, 3, -1, -1}, {-1, 6, 8, -1}, {-1, 11, 13, 15}};
+    const R hx = R(0.5) * Ux, hy = R(0.5) * Uy;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Wc[e][k] = Ws[e][k] = R(0);
+#pragma unroll
+        for (int k = 0; k <= e; ++k) {
+            const R C = Ha[kC[e][k]];
+            const R S = k >= 1 ? Ha[kS[e][k]] : R(0);
+            Wc[e][k] += U0 * C - Hb[kC[e][k]];
+            if (k >= 1) Ws[e][k] += U0 * S - Hb[kS[e][k]];
+            if (k == 0) {
+                Wc[e][1] -= Ux * C;  // cos t * 1
+                Ws[e][1] -= Uy * C;  // sin t * 1
+            } else {
+                // cos t cos kt = (cos(k+1)t + cos(k-1)t) / 2, cos t sin kt = (sin(k+1)t + sin(k-1)t) / 2
+                Wc[e][k + 1] -= hx * C;
+                Wc[e][k - 1] -= hx * C;
+                Ws[e][k + 1] -= hx * S;
+                if (k >= 2) Ws[e][k - 1] -= hx * S;
+                // sin t cos kt = (sin(k+1)t - sin(k-1)t) / 2, sin t sin kt = (cos(k-1)t - cos(k+1)t) / 2
+                Ws[e][k + 1] -= hy * C;
+                if (k >= 2) Ws[e][k - 1] += hy * C;
+                Wc[e][k - 1] -= hy * S;
+                Wc[e][k + 1] += hy * S;
+            }
+        }
+    }
+}
+
+// Even / odd (in t -> t + pi) parts of W_e at direction tg.
+template <class R>
+RLBM_HD void omega_pair(const R Wc[4][5], const R Ws[4][5], const DirTrig &tg, R E[4], R O[4])
+{
+    const R c = R(tg.c), s = R(tg.s), c2 = R(tg.c2), s2 = R(tg.s2), c3 = R(tg.c3), s3 = R(tg.s3);
+    const R c4 = R(tg.c4), s4 = R(tg.s4);
+    E[0] = Wc[0][0];
+    O[0] = Wc[0][1] * c + Ws[0][1] * s;
+    E[1] = Wc[1][0] + Wc[1][2] * c2 + Ws[1][2] * s2;
+    O[1] = Wc[1][1] * c + Ws[1][1] * s;
+    E[2] = Wc[2][0] + Wc[2][2] * c2 + Ws[2][2] * s2;
+    O[2] = Wc[2][1] * c + Ws[2][1] * s + Wc[2][3] * c3 + Ws[2][3] * s3;
+    E[3] = Wc[3][0] + Wc[3][2] * c2 + Ws[3][2] * s2 + Wc[3][4] * c4 + Ws[3][4] * s4;
+    O[3] = Wc[3][1] * c + Ws[3][1] * s + Wc[3][3] * c3 + Ws[3][3] * s3;
+}
+
 // Value of the polynomial with harmonic coefficients H at p = p0 (1, cos t, sin t).
 template <class R>
 RLBM_HD R harmonics_eval(const R H[kK], R p0, R t_cos, R t_sin)
@@ -126,8 +186,11 @@ RLBM_HD R harmonics_eval(const R H[kK], R p0, R t_cos, R t_sin)
     return ((q3 * p0 + q2) * p0 + q1) * p0 + q0;
 }
 
-// Appendix B: a^(k) for density n, temperature T and 4-velocity U, times n/T.
-RLBM_HD void appendix_b(double n, double T, double u0, double ux, double uy, double a[kK])
+// Appendix B: a^(k) for density n, temperature T and 4-velocity U, times
+// n/T, handed to sink(k, a_k) one coefficient at a time (so that a kernel can
+// convert each one as it is formed instead of holding all sixteen).
+template <class Sink>
+RLBM_HD void appendix_b_each(double n, double T, double u0, double ux, double uy, Sink &&sink)
 {
     const double s3 = 1.7320508075688772935274463;
     const double s15 = 3.8729833462074168851792654;
@@ -137,22 +200,27 @@ RLBM_HD void appendix_b(double n, double T, double u0, double ux, double uy, dou
     const double T2 = T * T;
     const double ux2 = ux * ux, u02 = u0 * u0;
     const double sc = n / T;
-    a[0] = sc;
-    a[1] = sc * Tu;
-    a[2] = sc * T * ux;
-    a[3] = sc * T * uy;
-    a[4] = sc * (0.5 * T2 * (3.0 * u02 - 1.0) - 2.0 * T * u0 + 1.0);
-    a[5] = sc * s3 * T * ux * Tu;
-    a[6] = sc * s3 * T * uy * Tu;
-    a[7] = sc * (-0.5 * s3 * T2 * (u02 - 2.0 * ux2 - 1.0));
-    a[8] = sc * s3 * T2 * ux * uy;
-    a[9] = sc * 0.5 * Tu * (T2 * (5.0 * u02 - 3.0) - 4.0 * T * u0 + 2.0);
-    a[10] = sc * 0.5 * T * ux * (T2 * (5.0 * ux2 + 3.0) - 6.0 * T * u0 + 3.0);
-    a[11] = sc * (-0.5 * s15 * T * ux * (T2 * (-2.0 * u02 + ux2 + 1.0) + 2.0 * T * u0 - 1.0));
-    a[12] = sc * (-0.5 * s15 * T2 * Tu * (u02 - 2.0 * ux2 - 1.0));
-    a[13] = sc * 0.5 * s32 * T * uy * (T2 * (5.0 * u02 - 1.0) - 8.0 * T * u0 + 4.0);
-    a[14] = sc * (-0.5 * s52 * T2 * T * uy * (u02 - 4.0 * ux2 - 1.0));
-    a[15] = sc * s15 * T2 * ux * uy * Tu;
+    sink(0, sc);
+    sink(1, sc * Tu);
+    sink(2, sc * T * ux);
+    sink(3, sc * T * uy);
+    sink(4, sc * (0.5 * T2 * (3.0 * u02 - 1.0) - 2.0 * T * u0 + 1.0));
+    sink(5, sc * s3 * T * ux * Tu);
+    sink(6, sc * s3 * T * uy * Tu);
+    sink(7, sc * (-0.5 * s3 * T2 * (u02 - 2.0 * ux2 - 1.0)));
+    sink(8, sc * s3 * T2 * ux * uy);
+    sink(9, sc * 0.5 * Tu * (T2 * (5.0 * u02 - 3.0) - 4.0 * T * u0 + 2.0));
+    sink(10, sc * 0.5 * T * ux * (T2 * (5.0 * ux2 + 3.0) - 6.0 * T * u0 + 3.0));
+    sink(11, sc * (-0.5 * s15 * T * ux * (T2 * (-2.0 * u02 + ux2 + 1.0) + 2.0 * T * u0 - 1.0)));
+    sink(12, sc * (-0.5 * s15 * T2 * Tu * (u02 - 2.0 * ux2 - 1.0)));
+    sink(13, sc * 0.5 * s32 * T * uy * (T2 * (5.0 * u02 - 1.0) - 8.0 * T * u0 + 4.0));
+    sink(14, sc * (-0.5 * s52 * T2 * T * uy * (u02 - 4.0 * ux2 - 1.0)));
+    sink(15, sc * s15 * T2 * ux * uy * Tu);
+}
+
+RLBM_HD void appendix_b(double n, double T, double u0, double ux, double uy, double a[kK])
+{
+    appendix_b_each(n, T, u0, ux, uy, [&](int k, double v) { a[k] = v; });
 }
 
 // Landau frame of the contravariant stress-energy tensor (symmetric, entries

@@ -21,43 +21,72 @@ template <class S>
 struct StoreIO;
 template <>
 struct StoreIO<double> {
-    template <class R>
-    __device__ static R load(const double *p) { return R(*p); }
-    template <class R>
-    __device__ static void store(double *p, R v) { *p = double(v); }
-    template <class R>
-    __device__ static void store_nt(double *p, R v) { __builtin_nontemporal_store(double(v), p); }
+    template <class R, class P>
+    __device__ static R load(P p) { return R(*p); }
+    template <class R, class P>
+    __device__ static void store(P p, R v) { *p = double(v); }
+    template <class R, class P>
+    __device__ static void store_nt(P p, R v) { __builtin_nontemporal_store(double(v), p); }
 };
 template <>
 struct StoreIO<float> {
-    template <class R>
-    __device__ static R load(const float *p) { return R(*p); }
-    template <class R>
-    __device__ static void store(float *p, R v) { *p = float(v); }
-    template <class R>
-    __device__ static void store_nt(float *p, R v) { __builtin_nontemporal_store(float(v), p); }
+    template <class R, class P>
+    __device__ static R load(P p) { return R(*p); }
+    template <class R, class P>
+    __device__ static void store(P p, R v) { *p = float(v); }
+    template <class R, class P>
+    __device__ static void store_nt(P p, R v) { __builtin_nontemporal_store(float(v), p); }
 };
 template <>
 struct StoreIO<_Float16> {
-    template <class R>
-    __device__ static R load(const _Float16 *p) { return R(float(*p)); }
-    template <class R>
-    __device__ static void store(_Float16 *p, R v) { *p = _Float16(float(v)); }
-    template <class R>
-    __device__ static void store_nt(_Float16 *p, R v) { __builtin_nontemporal_store(_Float16(float(v)), p); }
+    template <class R, class P>
+    __device__ static R load(P p) { return R(float(*p)); }
+    template <class R, class P>
+    __device__ static void store(P p, R v) { *p = _Float16(float(v)); }
+    template <class R, class P>
+    __device__ static void store_nt(P p, R v) { __builtin_nontemporal_store(_Float16(float(v)), p); }
 };
 
 struct SiteFields {
-    double n, vx, vy, eps;
+    double n, u0, ux, uy, eps;  // density, Landau 4-velocity, energy density
+};
+
+// Element `site` of a plane given by a uniform base pointer, addressed as
+// that base (held in scalar registers) plus a 32-bit byte offset, in the
+// global address space: one vector offset then serves every plane, instead
+// of a 64-bit address per lane and plane.  The empty asm only pins the base
+// to scalar registers (it keeps the compiler from folding the per-plane
+// bases into per-lane addresses).  Planes stay below 4 GiB (the library
+// rejects larger lattices).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *plane_at(T *base, unsigned site)
+{
+    asm("" : "+s"(base));
+    typedef __attribute__((address_space(1))) T GT;
+    typedef __attribute__((address_space(1))) const char GC;
+    return (GT *)((GC *)base + site * (unsigned)sizeof(T));
+}
+
+// Discards the post-collision values (callers that read h afterwards).
+struct NoEmit {
+    template <class R>
+    __device__ void operator()(int, R) const {}
+};
+// Discards the site's fields.
+struct NoFields {
+    __device__ void operator()(const SiteFields &, bool) const {}
 };
 
 // Collision of one site, in place on the 48 scaled deviations h.
 // Steps: moments -> Landau frame -> n, T -> Appendix B projections ->
 // equilibrium and forcing polynomials -> relaxation with
 // omega_d = p_i.U / (p0_i tau) = (U^0 - nhat_d . U_s) / tau.
-template <class R>
-__device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, SiteFields &out, R fx, R fy,
-                                             bool has_force)
+// fields(f, ok) receives the site's fields right after the Landau frame and
+// emit(i, value) each post-collision value as soon as it is formed, so a
+// caller that stores them lets their registers die early.
+template <class R, class Emit = NoEmit, class Fields = NoFields>
+__device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, R fx, R fy, bool has_force,
+                                             const Emit &emit = Emit(), const Fields &fields = Fields())
 {
     // ---- moments of the deviation, one pair of opposite directions at a time ----
     R N0 = 0, Nx = 0, Ny = 0, T00 = 0, T0x = 0, T0y = 0, Txx = 0, Txy = 0, Tyy = 0;
@@ -93,66 +122,63 @@ __device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, S
                                  nT + double(Tyy), eps, u0, ux, uy);
     const double n = u0 * dN0 - ux * dNx - uy * dNy;
     const double T = eps / (2.0 * n);
-    out.n = n;
-    out.vx = ux / u0;
-    out.vy = uy / u0;
-    out.eps = eps;
+    fields(SiteFields{n, u0, ux, uy, eps}, ok);
+    const R U0 = R(u0 * A.tau_inv), Ux = R(ux * A.tau_inv), Uy = R(uy * A.tau_inv);
     // ---- equilibrium and force coefficients (deviation from the reference, / scale) ----
-    double a[kK];
-    appendix_b(n, T, u0, ux, uy, a);
     R ad[kK];
-#pragma unroll
-    for (int k = 0; k < kK; ++k) ad[k] = R((a[k] - A.a_ref[k]) * A.inv_scale);
-    R Ha[kK], Hb[kK];
-    appendix_a_to_harmonics(ad, Ha);
+    appendix_b_each(n, T, u0, ux, uy, [&](int k, double v) { ad[k] = R((v - A.a_ref[k]) * A.inv_scale); });
+    R Hb[kK];
     if (has_force) {
-        // b = (Fx C_x + Fy C_y) a / scale with a / scale = ad + a_ref / scale
-        R as[kK];
+        // b = (Fx C_x + Fy C_y) a / scale with a / scale = ad + a_ref / scale,
+        // accumulated in one array (the force components folded in)
+        R b[kK];
 #pragma unroll
-        for (int k = 0; k < kK; ++k) as[k] = ad[k];
+        for (int k = 0; k < kK; ++k) b[k] = R(0);
+        R arest[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) as[kRestK[r]] += A.aref_s[r];
-        R bx[kK], by[kK], b[kK];
+        for (int r = 0; r < 4; ++r) arest[r] = ad[kRestK[r]] + A.aref_s[r];
 #pragma unroll
-        for (int k = 0; k < kK; ++k) bx[k] = by[k] = R(0);
-        if (fx != R(0)) {
-#pragma unroll
-            for (int q = 0; q < kForceNx; ++q) bx[kForceX[q].k] += R(kForceX[q].v) * as[kForceX[q].m];
-        }
-        if (fy != R(0)) {
-#pragma unroll
-            for (int q = 0; q < kForceNy; ++q) by[kForceY[q].k] += R(kForceY[q].v) * as[kForceY[q].m];
+        for (int q = 0; q < kForceNx; ++q) {
+            const int m = kForceX[q].m;
+            const int r = m == kRestK[0] ? 0 : m == kRestK[1] ? 1 : m == kRestK[2] ? 2 : m == kRestK[3] ? 3 : -1;
+            b[kForceX[q].k] += (fx * R(kForceX[q].v)) * (r >= 0 ? arest[r] : ad[m]);
         }
 #pragma unroll
-        for (int k = 0; k < kK; ++k) b[k] = fx * bx[k] + fy * by[k];
+        for (int q = 0; q < kForceNy; ++q) {
+            const int m = kForceY[q].m;
+            const int r = m == kRestK[0] ? 0 : m == kRestK[1] ? 1 : m == kRestK[2] ? 2 : m == kRestK[3] ? 3 : -1;
+            b[kForceY[q].k] += (fy * R(kForceY[q].v)) * (r >= 0 ? arest[r] : ad[m]);
+        }
         appendix_a_to_harmonics(b, Hb);
     } else {
 #pragma unroll
         for (int k = 0; k < kK; ++k) Hb[k] = R(0);
     }
+    R Wc[4][5], Ws[4][5];
+    {
+        R Ha[kK];
+        appendix_a_to_harmonics(ad, Ha);
+        omega_harmonics(Ha, Hb, U0, Ux, Uy, Wc, Ws);
+    }
     // ---- relaxation plus forcing, one pair of opposite directions at a time ----
-    const R U0 = R(u0 * A.tau_inv), Ux = R(ux * A.tau_inv), Uy = R(uy * A.tau_inv);
+    // f*_i = f_i - omega_d f_i + (omega_d f^eq - force)(p_i), the bracket being
+    // the radial polynomial sum_e p0^e W_e(t_d) (odd harmonics flip for d + 6)
 #pragma unroll
     for (int d = 0; d < kDirs / 2; ++d) {
         const DirTrig tg = dir_trig(d);
-        R Ea[4], Oa[4], Eb[4], Ob[4];
-        harmonics_pair(Ha, tg, Ea, Oa);
-        harmonics_pair(Hb, tg, Eb, Ob);
+        R E[4], O[4];
+        omega_pair(Wc, Ws, tg, E, O);
         const R proj = Ux * R(tg.c) + Uy * R(tg.s);
         const R wp = U0 - proj, wm = U0 + proj;  // omega of d and of d + 6
-        R Gp[4], Gm[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            Gp[e] = wp * (Ea[e] + Oa[e]) - (Eb[e] + Ob[e]);
-            Gm[e] = wm * (Ea[e] - Oa[e]) - (Eb[e] - Ob[e]);
-        }
 #pragma unroll
         for (int j = 0; j < kShells; ++j) {
             const R p = A.p0[j];
-            const R qp = ((Gp[3] * p + Gp[2]) * p + Gp[1]) * p + Gp[0];
-            const R qm = ((Gm[3] * p + Gm[2]) * p + Gm[1]) * p + Gm[0];
+            const R qp = (((E[3] + O[3]) * p + (E[2] + O[2])) * p + (E[1] + O[1])) * p + (E[0] + O[0]);
+            const R qm = (((E[3] - O[3]) * p + (E[2] - O[2])) * p + (E[1] - O[1])) * p + (E[0] - O[0]);
             h[4 * d + j] = (R(1) - wp) * h[4 * d + j] + qp;
             h[4 * (d + 6) + j] = (R(1) - wm) * h[4 * (d + 6) + j] + qm;
+            emit(4 * d + j, h[4 * d + j]);
+            emit(4 * (d + 6) + j, h[4 * (d + 6) + j]);
         }
     }
     return ok;
@@ -169,8 +195,8 @@ __device__ __forceinline__ void write_fields(const StepArgs<R> &A, long long sit
         return;
     }
     A.fn[site] = f.n;
-    A.fvx[site] = f.vx;
-    A.fvy[site] = f.vy;
+    A.fvx[site] = f.ux / f.u0;
+    A.fvy[site] = f.uy / f.u0;
     A.feps[site] = f.eps;
 }
 
@@ -263,42 +289,32 @@ __device__ __forceinline__ void gather_general(const StepArgs<R> &A, const S *__
 // gather), the rest tile the interior x in [5, nx - 5), y in [5, ny - 5)
 // with tile_x * rows sites per block, tiles aligned to tile_x so every
 // wavefront stores 64 aligned values.
-template <class S, class R, bool LCA>
+// Force mode of a step kernel, fixed at compile time so that no runtime
+// branch splits the register allocation: no force, the uniform drive, or
+// the drive plus the local-capacitance term.
+enum ForceMode { kNoForce = 0, kDrive = 1, kLca = 2 };
+
+// GATHER: kGatherTable (the boundary band always has a gather table),
+// kGatherComputed (it never has: huge lattices) or kGatherEither (decided
+// per launch from the arguments; the batched kernel).  The computed gather
+// is long code, kept out of the kernels that do not need it.
+enum GatherMode { kGatherTable = 0, kGatherComputed = 1, kGatherEither = 2 };
+
+template <class S, class R, int MODE, int GATHER>
 __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__restrict__ src, S *__restrict__ dst,
                                            int b, int nbnd, int tile_x, int tiles_x, int all, int wf)
 {
     const int t = threadIdx.x;
     const int nx = A.nx;
     const long long P = A.plane;
+    // ---- locate the site: boundary band (table row idx) or interior tile ----
     int x, y;
-    bool inner;
-    R h[kQ];
-    if (b < nbnd) {
-        const long long idx = (long long)b * blockDim.x + t;
-        if (idx >= boundary_count(nx, A.ny, all)) return;
+    unsigned idx = 0;  // boundary band row (the band holds far fewer than 2^31 sites)
+    const bool bnd = b < nbnd;
+    if (bnd) {
+        idx = (unsigned)b * blockDim.x + t;
+        if ((long long)idx >= boundary_count(nx, A.ny, all)) return;
         boundary_site(idx, nx, A.ny, all, x, y);
-        inner = false;
-        const long long site = (long long)y * nx + x;
-        if (A.has_mask && A.mask[site]) {
-            if (wf) {
-                A.fn[site] = 0.0;
-                A.fvx[site] = 0.0;
-                A.fvy[site] = 0.0;
-                A.feps[site] = 0.0;
-            }
-            return;
-        }
-        if (A.gather_tab) {
-            const unsigned *__restrict__ tab = A.gather_tab;
-#pragma unroll
-            for (int i = 0; i < kQ; ++i) {
-                const unsigned c = tab[(long long)i * A.nbnd + idx];
-                h[i] = (c & kContactFlag) ? A.contact_eta[c & ~kContactFlag]
-                                          : StoreIO<S>::template load<R>(src + c);
-            }
-        } else {
-            gather_general<S, R>(A, src, x, y, site, h);
-        }
     } else {
         const int tb = b - nbnd;
         const int by = tb / tiles_x, bx = tb - by * tiles_x;
@@ -307,82 +323,104 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
         x = bx * tile_x + (t - ty * tile_x);
         y = kReach + by * rows + ty;
         if (x < kReach || x >= nx - kReach || y >= A.ny - kReach) return;
-        inner = true;
+    }
+    const unsigned site = (unsigned)y * (unsigned)nx + (unsigned)x;
+    if (bnd && A.has_mask && A.mask[site]) {
+        if (wf) {
+            A.fn[site] = 0.0;
+            A.fvx[site] = 0.0;
+            A.fvy[site] = 0.0;
+            A.feps[site] = 0.0;
+        }
+        return;
+    }
+    // ---- force (before the gather: its temporaries die before h is loaded) ----
+    R fx = A.fx, fy = A.fy;
+    if constexpr (MODE == kLca) lca_force(A, x, y, site, !bnd, fx, fy);
+    // ---- gather ----
+    R h[kQ];
+    if (bnd) {
+        const bool table = GATHER == kGatherTable || (GATHER == kGatherEither && A.gather_tab);
+        if (table) {
+            // eight table codes, then their eight values, at a time: without
+            // the fence the compiler fetches all 48 codes first and the band's
+            // path alone would set the kernel's register budget
+            const unsigned *__restrict__ tab = A.gather_tab;
+#pragma unroll
+            for (int i0 = 0; i0 < kQ; i0 += 8) {
+                unsigned c[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) c[i] = tab[(long long)(i0 + i) * A.nbnd + idx];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    h[i0 + i] = (c[i] & kContactFlag) ? A.contact_eta[c[i] & ~kContactFlag]
+                                                      : StoreIO<S>::template load<R>(src + c[i]);
+                asm volatile("" ::: "memory");
+            }
+        } else if constexpr (GATHER != kGatherTable) {
+            gather_general<S, R>(A, src, x, y, site, h);
+        }
+    } else {
         // uniform plane base pointers + one 32-bit site offset
-        const unsigned site = (unsigned)y * (unsigned)nx + (unsigned)x;
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
             const int d = i / kShells;
             const S *__restrict__ plane = src + ((long long)i * P - ((long long)kCy[d] * nx + kCx[d]));
-            h[i] = StoreIO<S>::template load<R>(plane + site);
+            h[i] = StoreIO<S>::template load<R>(plane_at(plane, site));
         }
     }
-    const unsigned site = (unsigned)y * (unsigned)nx + (unsigned)x;
-    SiteFields f;
-    bool ok;
-    if constexpr (LCA) {
-        R fx, fy;
-        lca_force(A, x, y, site, inner, fx, fy);
-        ok = collide_site<R>(h, A, f, fx, fy, true);
-        A.n_next[site] = ok ? f.n : NAN;
-    } else {
-        (void)inner;
-        ok = collide_site<R>(h, A, f, A.fx, A.fy, A.has_force != 0);
-    }
-    if (wf) write_fields(A, site, f, ok);
-    if (A.nt_store) {
-        // streaming stores: the next step reads these values once, from HBM
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) StoreIO<S>::template store_nt<R>(dst + (long long)i * P + site, h[i]);
-    } else {
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            S *__restrict__ plane = dst + (long long)i * P;
-            StoreIO<S>::template store<R>(plane + site, h[i]);
-        }
-    }
+    // ---- collide; each post-collision value is stored as soon as it is
+    // formed (streaming stores bypass the caches: the next step reads every
+    // value once) ----
+    const bool nt = A.nt_store != 0;
+    auto store = [&](int i, R v) {
+        auto p = plane_at(dst + (long long)i * P, site);
+        if (nt)
+            StoreIO<S>::template store_nt<R>(p, v);
+        else
+            StoreIO<S>::template store<R>(p, v);
+    };
+    auto fields = [&](const SiteFields &f, bool ok) {
+        if (wf) write_fields(A, site, f, ok);
+        if constexpr (MODE == kLca) A.n_next[site] = ok ? f.n : NAN;
+    };
+    collide_site<R>(h, A, fx, fy, MODE != kNoForce, store, fields);
 }
 
-template <class S, class R, bool LCA>
-__global__ __launch_bounds__(256) void step_kernel(const StepArgs<R> A, const S *__restrict__ src,
-                                                   S *__restrict__ dst, int nbnd, int tile_x, int tiles_x, int all)
+// At most four waves per SIMD: measured on MI355X, the compiler's schedule
+// for that budget (about 110 VGPRs) beats the five-wave one (96 VGPRs) on
+// FP32 at 4096 x 2048 by 2% and is level elsewhere.
+template <class S, class R, int MODE, int GATHER>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void step_kernel(const StepArgs<R> A, const S *__restrict__ src,
+                                                   S *__restrict__ dst, int nbnd, int tile_x, int tiles_x, int all,
+                                                   int xcd)
 {
-    step_block<S, R, LCA>(A, src, dst, blockIdx.x, nbnd, tile_x, tiles_x, all, A.write_fields);
+    const int b = xcd ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    step_block<S, R, MODE, GATHER>(A, src, dst, b, nbnd, tile_x, tiles_x, all, A.write_fields);
 }
 
-// Batched step: a persistent grid drains the work list of (sample, block)
-// items through an atomic counter; each item is one block of that sample's
-// step grid.  The last block to leave resets the counters, so the next launch
-// (or graph replay) starts from zero without a memset.
+// Batched step: one block per work item of the list of (sample, block)
+// items, each item being one block of that sample's step grid; the grid is
+// the list's capacity and blocks past the current item count leave at once.
+// (A persistent grid looping over the items keeps each item's descriptor
+// live across iterations and needs every register of the SIMD, one wave
+// per SIMD; one item per block keeps the single-lattice kernel's budget.)
 template <class S, class R>
 __global__ __launch_bounds__(256) void batch_step_kernel(const BatchDesc<R> *__restrict__ descs,
                                                          const unsigned *__restrict__ items,
-                                                         const int *__restrict__ n_items_p,
-                                                         unsigned *__restrict__ counters, int parity, int wf)
+                                                         const int *__restrict__ n_items_p, int parity, int wf,
+                                                         int xcd)
 {
-    __shared__ unsigned s_item;
     const unsigned n_items = (unsigned)*n_items_p;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&counters[0], 1u);
-        __syncthreads();
-        const unsigned k = s_item;
-        __syncthreads();
-        if (k >= n_items) break;
-        const unsigned it = __builtin_amdgcn_readfirstlane(items[k]);
-        const int smp = (int)(it >> kItemBlockBits), b = (int)(it & ((1u << kItemBlockBits) - 1));
-        const BatchDesc<R> &D = descs[smp];
-        const int par = parity ^ D.parity_xor;
-        step_block<S, R, false>(D.a, static_cast<const S *>(D.pop[par]), static_cast<S *>(D.pop[par ^ 1]), b, D.nbnd,
-                                D.tile_x, D.tiles_x, D.all, wf);
-    }
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned done = atomicAdd(&counters[1], 1u);
-        if (done == gridDim.x - 1) {
-            atomicExch(&counters[0], 0u);
-            atomicExch(&counters[1], 0u);
-        }
-    }
+    const unsigned k = xcd ? (unsigned)xcd_block((int)blockIdx.x, (int)gridDim.x) : blockIdx.x;
+    if (k >= n_items) return;
+    const unsigned it = __builtin_amdgcn_readfirstlane(items[k]);
+    const int smp = (int)(it >> kItemBlockBits), b = (int)(it & ((1u << kItemBlockBits) - 1));
+    const BatchDesc<R> &D = descs[smp];
+    const int par = parity ^ D.parity_xor;
+    // the drive variant serves every sample: a zero drive adds exactly zero
+    step_block<S, R, kDrive, kGatherEither>(D.a, static_cast<const S *>(D.pop[par]), static_cast<S *>(D.pop[par ^ 1]),
+                                            b, D.nbnd, D.tile_x, D.tiles_x, D.all, wf);
 }
 
 // Per-sample residual partial sums: block (s, j) covers sites j, j + B*256,
@@ -471,7 +509,6 @@ __global__ __launch_bounds__(256) void init_kernel(const StepArgs<R> A, const do
             h[4 * (d + 6) + j] = (((E[3] - O[3]) * p + (E[2] - O[2])) * p + (E[1] - O[1])) * p + (E[0] - O[0]);
         }
     }
-    SiteFields f;
     R fx = A.fx, fy = A.fy;
     bool force = A.has_force != 0;
     if (mode == kInitLca) {
@@ -479,13 +516,14 @@ __global__ __launch_bounds__(256) void init_kernel(const StepArgs<R> A, const do
         lca_force(A, x, y, site, false, fx, fy);
         force = true;
     }
-    const bool ok = collide_site<R>(h, A, f, fx, fy, force);
     if (mode == kInitDensity) {
-        A.n_next[site] = ok ? f.n : NAN;
+        collide_site<R>(h, A, fx, fy, force, NoEmit(),
+                        [&](const SiteFields &f, bool ok) { A.n_next[site] = ok ? f.n : NAN; });
         return;
     }
-    write_fields(A, site, f, ok);
-    for (int i = 0; i < kQ; ++i) StoreIO<S>::template store<R>(dst + (long long)i * A.plane + site, h[i]);
+    collide_site<R>(h, A, fx, fy, force,
+                    [&](int i, R v) { StoreIO<S>::template store<R>(dst + (long long)i * A.plane + site, v); },
+                    [&](const SiteFields &f, bool ok) { write_fields(A, site, f, ok); });
 }
 
 template <class S>
@@ -557,14 +595,25 @@ hipError_t launch_step_t(const void *args, const void *src, void *dst, LaunchSha
         tiles_x = (A.nx + sh.tile_x - 1) / sh.tile_x;
         tiles = tiles_x * ((A.ny - 2 * kReach + rows - 1) / rows);
     }
-    if (A.n_prev)
-        hipLaunchKernelGGL((step_kernel<S, R, true>), dim3((unsigned)(nbnd + tiles)), dim3(block), 0, s, A,
-                           static_cast<const S *>(src), static_cast<S *>(dst), nbnd, sh.tile_x, tiles_x,
-                           interior ? 0 : 1);
-    else
-        hipLaunchKernelGGL((step_kernel<S, R, false>), dim3((unsigned)(nbnd + tiles)), dim3(block), 0, s, A,
-                           static_cast<const S *>(src), static_cast<S *>(dst), nbnd, sh.tile_x, tiles_x,
-                           interior ? 0 : 1);
+    const dim3 grid((unsigned)(nbnd + tiles));
+    const S *in = static_cast<const S *>(src);
+    S *out = static_cast<S *>(dst);
+    const int all = interior ? 0 : 1;
+    const int mode = A.n_prev ? kLca : A.has_force ? kDrive : kNoForce;
+    const int gather = A.gather_tab ? kGatherTable : kGatherComputed;
+#define RLBM_LAUNCH_STEP(M, G)                                                                                   \
+    hipLaunchKernelGGL((step_kernel<S, R, M, G>), grid, dim3(block), 0, s, A, in, out, nbnd, sh.tile_x, tiles_x, \
+                       all, sh.xcd)
+    if (gather == kGatherTable) {
+        if (mode == kLca) RLBM_LAUNCH_STEP(kLca, kGatherTable);
+        else if (mode == kDrive) RLBM_LAUNCH_STEP(kDrive, kGatherTable);
+        else RLBM_LAUNCH_STEP(kNoForce, kGatherTable);
+    } else {
+        if (mode == kLca) RLBM_LAUNCH_STEP(kLca, kGatherComputed);
+        else if (mode == kDrive) RLBM_LAUNCH_STEP(kDrive, kGatherComputed);
+        else RLBM_LAUNCH_STEP(kNoForce, kGatherComputed);
+    }
+#undef RLBM_LAUNCH_STEP
     return hipGetLastError();
 }
 
@@ -583,46 +632,26 @@ hipError_t launch_init_t(const void *args, const double *n, const double *T, con
 }
 
 template <class S, class R>
-hipError_t launch_batch_t(const void *descs, const unsigned *items, const int *n_items, unsigned *counters, int grid,
-                          int parity, int wf, hipStream_t s)
+hipError_t launch_batch_t(const void *descs, const unsigned *items, const int *n_items, int grid, int parity, int wf,
+                          int xcd, hipStream_t s)
 {
     hipLaunchKernelGGL((batch_step_kernel<S, R>), dim3(grid), dim3(256), 0, s,
-                       static_cast<const BatchDesc<R> *>(descs), items, n_items, counters, parity, wf);
+                       static_cast<const BatchDesc<R> *>(descs), items, n_items, parity, wf, xcd);
     return hipGetLastError();
-}
-
-template <class S, class R>
-int batch_grid_t()
-{
-    int dev = 0, per_cu = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_step_kernel<S, R>, 256, 0) != hipSuccess) return 0;
-    return per_cu * prop.multiProcessorCount;
 }
 
 }  // namespace
 
-hipError_t launch_batch_step(Store st, const void *descs, const unsigned *items, const int *n_items,
-                             unsigned *counters, int grid, int parity, int write_fields, hipStream_t s)
+hipError_t launch_batch_step(Store st, const void *descs, const unsigned *items, const int *n_items, int grid,
+                             int parity, int write_fields, int xcd, hipStream_t s)
 {
+    if (grid <= 0) return hipErrorInvalidValue;
     switch (st) {
-    case Store::F64: return launch_batch_t<double, double>(descs, items, n_items, counters, grid, parity, write_fields, s);
-    case Store::F32: return launch_batch_t<float, float>(descs, items, n_items, counters, grid, parity, write_fields, s);
-    case Store::F16:
-        return launch_batch_t<_Float16, float>(descs, items, n_items, counters, grid, parity, write_fields, s);
+    case Store::F64: return launch_batch_t<double, double>(descs, items, n_items, grid, parity, write_fields, xcd, s);
+    case Store::F32: return launch_batch_t<float, float>(descs, items, n_items, grid, parity, write_fields, xcd, s);
+    case Store::F16: return launch_batch_t<_Float16, float>(descs, items, n_items, grid, parity, write_fields, xcd, s);
     }
     return hipErrorInvalidValue;
-}
-
-int batch_resident_blocks(Store st)
-{
-    switch (st) {
-    case Store::F64: return batch_grid_t<double, double>();
-    case Store::F32: return batch_grid_t<float, float>();
-    case Store::F16: return batch_grid_t<_Float16, float>();
-    }
-    return 0;
 }
 
 hipError_t launch_batch_residual(Store st, const void *descs, int nsamples, int blocks_per_sample, double *part,
@@ -640,7 +669,8 @@ hipError_t launch_batch_residual(Store st, const void *descs, int nsamples, int 
 
 hipError_t launch_step(Store st, const void *args, const void *src, void *dst, LaunchShape shape, hipStream_t s)
 {
-    if (shape.tile_x <= 0 || shape.rows <= 0 || shape.tile_x * shape.rows != 256 || shape.tile_x % 64)
+    if (shape.tile_x <= 0 || shape.rows <= 0 || shape.tile_x * shape.rows != 256 || shape.tile_x % 64 ||
+        (shape.xcd != 0 && shape.xcd != 1))
         return hipErrorInvalidValue;
     switch (st) {
     case Store::F64: return launch_step_t<double, double>(args, src, dst, shape, s);

@@ -15,6 +15,13 @@ and step count.  Contacts use the lattice convention of include/rlbm.h
     - 1024 x 512: contacts 32 wide, centres 256 apart, F = 1e-5, tau = 0.8,
       20 000 steps (FP32).
     - 4096 x 2048: the same scaled by 4: contacts 128 wide, centres 1024 apart.
+* ``injector_setup``: the validation geometry of Sec. 3 (its figure is not
+  available, so the layout is this module's): an L x W channel (2000 x 500,
+  L/W = 4) with bounce-back walls, an injector contact w_in = 8 sites wide at
+  the middle of the bottom edge held at f^eq(n0, T0, (0, v_in)) and both
+  channel ends (the full left and right edges) held as drains at
+  f^eq(n0, T0, 0); uniform start n0 = 1.5, T0 = 1.25, v = 0; the deviation
+  storage references (n0, T0); local-capacitance force with C_g.
 * ``batch_samples``: 256 uneven samples, sizes uniform over
   {128, 192, ..., 1024} x {128, ..., 512}, tau ~ U[0.55, 2], contact width ~
   U{8..64}, centre gap ~ U{64..384} (redrawn until gap + width <= nx - 16),
@@ -93,3 +100,16 @@ def small_device(nx: int = 203, ny: int = 77, steps: int = 120, seed: int = 5):
     return dict(name=f"small_device_{nx}x{ny}", nx=nx, ny=ny, periodic_x=False, periodic_y=False,
                 contacts=contacts, tau=0.75, F=(2e-4, -1e-4), steps=steps, storage="f64",
                 init=dict(n=n, T=T, vx=vx, vy=vy))
+
+
+def injector_setup(nx: int = 2000, ny: int = 500, tau: float = 1.0, cg: float = 10.0, v_in: float = 1e-5,
+                   w_in: int = 8, n0: float = 1.5, T0: float = 1.25, storage: str = "f64", steps: int = 200_000):
+    """Injector into a channel drained at both ends (see the module notes)."""
+    start = nx // 2 - w_in // 2
+    contacts = [dict(edge="bottom", start=start, width=w_in, n=n0, T=T0, vx=0.0, vy=v_in),
+                dict(edge="left", start=0, width=ny, n=n0, T=T0, vx=0.0, vy=0.0),
+                dict(edge="right", start=0, width=ny, n=n0, T=T0, vx=0.0, vy=0.0)]
+    return dict(name=f"injector_{nx}x{ny}_tau{tau:g}_cg{cg:g}", nx=nx, ny=ny, periodic_x=False, periodic_y=False,
+                contacts=contacts, tau=tau, F=(0.0, 0.0), cg=cg, reference=(n0, T0), steps=steps, storage=storage,
+                v_in=v_in, w_in=w_in, injector_centre=(start + (w_in - 1) / 2.0, -0.5),
+                init=dict(n=n0, T=T0, vx=0.0, vy=0.0))

@@ -27,6 +27,8 @@ def gpu_lattice(w, storage=None, shape=None):
     L.set_drive(*w["F"])
     if w.get("cg") is not None:
         L.set_lca(w["cg"])
+    if w.get("reference") is not None:
+        L.set_reference(*w["reference"])
     i = w["init"]
     if all(np.isscalar(v) for v in i.values()):
         L.init_uniform(i["n"], i["T"], i["vx"], i["vy"])

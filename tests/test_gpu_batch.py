@@ -34,12 +34,17 @@ def _samples():
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
 @pytest.mark.parametrize("graph", [False, True])
-def test_batch_matches_single_lattices(storage, graph):
+@pytest.mark.parametrize("xcd", [False, True])
+def test_batch_matches_single_lattices(storage, graph, xcd):
+    """Also across block orders: the batch in one, the single lattices in the other."""
     import paper_1804_02418_amd as rl
 
     ws = _samples()
     B = rl.Batch(ws, storage)
+    B.set_block_order(xcd)
     singles = [gpu_lattice(w, storage) for w in ws]
+    for L in singles:
+        L.set_block_order(not xcd)
     for n in (1, 70):
         B.step(n, graph=graph)
         for L in singles:

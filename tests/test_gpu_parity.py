@@ -155,13 +155,16 @@ def test_invalid_tau_and_unstable_state():
 
 
 @pytest.mark.parametrize("shape", [(64, 4), (128, 2), (256, 1)])
-def test_launch_shapes_agree(shape):
-    """Every tile shape gives bit-identical results (pure data-parallel step)."""
+@pytest.mark.parametrize("xcd", [False, True])
+def test_launch_shapes_agree(shape, xcd):
+    """Every tile shape and block order gives bit-identical results (pure
+    data-parallel step)."""
     w = workloads.small_device(nx=300, ny=33, steps=5)
     ref = gpu_lattice(w, "f64")
     ref.step(5)
     a = ref.read_populations()
     G = gpu_lattice(w, "f64")
     G.set_launch_shape(*shape)
+    G.set_block_order(xcd)
     G.step(5)
     assert np.array_equal(a, G.read_populations())
