@@ -269,6 +269,61 @@ def batch_throughput(storage: str = "f32", count: int = 256, steps: int = 100, w
     return out
 
 
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
+
+
+def surrogate_throughput(batch: int = 8, size: int = 256, steps: int = 20, warmup: int = 3):
+    """Training-step and inference throughput of the warm-start U-Net (base
+    16, 16 input and 3 output channels) on a batch of random 256 x 256
+    images: forward, loss, backward and Adam per training step, HIP events
+    on the network's stream (torch's current stream).  FLOPs are the
+    convolutions' multiply-adds (3 x forward for a training step)."""
+    import torch
+
+    from paper_1804_02418_amd import _binding as B
+    from paper_1804_02418_amd import surrogate as S
+
+    torch.manual_seed(0)
+    net = B.UNet(16, S.CIN, S.COUT, size, size, max_batch=batch)
+    x = torch.randn((batch, size, size, S.CIN), device="cuda")
+    y = torch.randn((batch, size, size, S.COUT), device="cuda")
+    out = torch.empty_like(y)
+    dy = torch.empty_like(y)
+    stream = torch.cuda.current_stream()
+
+    def train_step():
+        net.forward(x, out)
+        net.mse(out, y, dy)
+        net.zero_grad()
+        net.backward(dy)
+        net.adam_step(1e-4)
+
+    def timed(fn, n):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(n):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / n
+
+    ms_train = timed(train_step, steps)
+    ms_infer = timed(lambda: net.forward(x, out), steps)
+    nparam = net.nparam
+    net.close()
+    fwd = S.forward_flops(16, S.CIN, S.COUT, size, size) * batch
+    return {"batch": batch, "size": size, "params": int(nparam),
+            "ms_per_train_step": round(ms_train, 3), "ms_per_forward": round(ms_infer, 3),
+            "train_tflops": round(3 * fwd / (ms_train / 1e3) / 1e12, 2),
+            "forward_tflops": round(fwd / (ms_infer / 1e3) / 1e12, 2),
+            "peak_bf16_tflops": PEAK_BF16_TFLOPS,
+            "forward_frac": round(fwd / (ms_infer / 1e3) / 1e12 / PEAK_BF16_TFLOPS, 4)}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,6 +335,8 @@ def main(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=200, help="oracle steps for the CPU baseline (0 = skip)")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the surrogate warm- vs cold-start timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-sample batched-kernel throughput")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate network throughput")
+    ap.add_argument("--surrogate-only", action="store_true", help="only time the surrogate network")
     ap.add_argument("--variants", action="store_true", help="also time the other storages and 4096x2048")
     ap.add_argument("--copy-bytes", type=int, default=0, help="only run the copy-bandwidth calibration")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch shape")
@@ -287,6 +344,9 @@ def main(argv=None):
 
     if args.copy_bytes:
         print(json.dumps(copy_calibration(args.copy_bytes)), flush=True)
+        return 0
+    if args.surrogate_only:
+        print(json.dumps({"surrogate": surrogate_throughput()}), flush=True)
         return 0
 
     if args.gpus != 1:
@@ -335,6 +395,8 @@ def main(argv=None):
         out["variants_mlups"] = extra
     if not args.no_batch:
         out["batch_256"] = batch_throughput(args.storage)
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_throughput()
     if not args.no_warm_start and os.path.exists(WEIGHTS):
         out["time_to_steady"] = warm_vs_cold(WEIGHTS)
     if args.cpu_steps > 0:

@@ -150,6 +150,24 @@ def predict(net, X, batch):
     return np.concatenate(preds)
 
 
+# Layer plan of the library's U-Net (level = resolution halvings, input and
+# output channels, kernel size), in the library's order: encoder, bottleneck,
+# decoder (its first conv of each level sees the concatenated skip), head.
+def layer_plan(base: int, cin: int, cout: int):
+    c0, c1, c2, c3 = base, 2 * base, 4 * base, 8 * base
+    return [(0, cin, c0, 3), (0, c0, c0, 3), (1, c0, c1, 3), (1, c1, c1, 3), (2, c1, c2, 3), (2, c2, c2, 3),
+            (3, c2, c3, 3), (3, c3, c3, 3), (4, c3, c3, 3), (4, c3, c3, 3), (3, 2 * c3, c3, 3), (3, c3, c3, 3),
+            (2, c3 + c2, c2, 3), (2, c2, c2, 3), (1, c2 + c1, c1, 3), (1, c1, c1, 3), (0, c1 + c0, c0, 3),
+            (0, c0, c0, 3), (0, c0, cout, 1)]
+
+
+def forward_flops(base: int, cin: int, cout: int, H: int, W: int) -> int:
+    """Multiply-add FLOPs (2 per MAC) of the convolutions of one forward pass
+    of one sample; a training step does about three times as many (forward,
+    gradient of the data, gradient of the weights)."""
+    return sum(2 * (H >> lv) * (W >> lv) * ci * co * k * k for lv, ci, co, k in layer_plan(base, cin, cout))
+
+
 def channel_scales(Y) -> np.ndarray:
     return np.maximum(Y.reshape(-1, Y.shape[-1]).std(axis=0), 1e-12).astype(np.float32)
 
