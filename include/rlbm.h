@@ -49,7 +49,8 @@ typedef enum {
     RLBM_ENOMEM = -2,    /* device or host allocation failed */
     RLBM_EDEVICE = -3,   /* a HIP call failed */
     RLBM_ESTATE = -4,    /* call out of order (e.g. step before init) */
-    RLBM_EUNSTABLE = -5  /* health check: non-finite value, n <= 0 or |u| >= 1 somewhere */
+    RLBM_EUNSTABLE = -5, /* health check: non-finite value, n <= 0 or |u| >= 1 somewhere */
+    RLBM_ENOTFOUND = -6  /* a search (rlbm_quadrature.h) found no admissible solution */
 } rlbm_status;
 
 /* Storage of the populations.  All three store the deviation
@@ -143,6 +144,16 @@ rlbm_status rlbm_set_drive(rlbm_lattice *lat, double Fx, double Fy);
  * are none).  Costs one extra 8-byte density read and write per site and
  * step.  Lattices with the term on cannot be stepped in a batch. */
 rlbm_status rlbm_set_lca(rlbm_lattice *lat, double inv_cg);
+
+/* Use another member of the family of massless third-order quadratures on
+ * the 48-node stencil (Sec. 2.3; the solutions form a two-parameter family,
+ * see rlbm_quadrature_massless in rlbm_quadrature.h): w1[4] are the weights
+ * of the (+-3,+-4)_FS directions, w2[4] of (+-5,0)_FS, p0[4] the shell
+ * energies (host arrays).  Checked on the host: weights >= 0, energies > 0,
+ * and Eq. `orthonormal` (every monomial condition of degree <= 6, each
+ * relative to max(|moment|, 1)) to 1e-12, else RLBM_EINVAL.  The lattice
+ * becomes uninitialised: call rlbm_init_* next. */
+rlbm_status rlbm_set_quadrature(rlbm_lattice *lat, const double w1[4], const double w2[4], const double p0[4]);
 
 /* Reference state of the deviation storage: f_ref_i = f^eq_i(n_ref, T_ref, 0)
  * and the stored value is (f_i - f_ref_i) / (w_i * scale).  Must be called

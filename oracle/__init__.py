@@ -96,8 +96,8 @@ def _iptr(a: np.ndarray):
 class Stencil:
     """The 48-node quadrature with its Appendix A table and force matrices."""
 
-    def __init__(self, use_printed: bool = False):
-        nodes = quadrature.node_table(use_printed)
+    def __init__(self, use_printed: bool = False, shells=None):
+        nodes = quadrature.node_table(use_printed, shells)
         self.nodes = nodes
         self.w = np.array(nodes["w"], dtype=np.float64)
         self.p0 = np.array(nodes["p0"], dtype=np.float64)

@@ -127,8 +127,15 @@ def _min_norm_step(jac, r, rel_cut=mp.mpf("1e-8")):
 @functools.lru_cache(maxsize=1)
 def polished(dps: int = 50):
     """Polish the printed quadrature; returns a dict of mpmath values and diagnostics."""
+    return solve_from(tuple(PRINTED_W1 + PRINTED_W2 + PRINTED_P0), dps)
+
+
+def solve_from(start, dps: int = 50):
+    """The solution of the conditions nearest (minimum-norm Gauss-Newton) to
+    start = (w1[4], w2[4], p0[4]) flattened; from the printed values this is
+    the polish, from elsewhere another member of the solution family."""
     with mp.workdps(dps):
-        x = mp.matrix([mp.mpf(s) for s in PRINTED_W1 + PRINTED_W2 + PRINTED_P0])
+        x = mp.matrix([mp.mpf(s) for s in start])
         x_printed = x.copy()
         r0, _ = _residual_and_jacobian(x)
         res_printed = max(abs(v) for v in r0)
@@ -168,13 +175,14 @@ def shell_tables(use_printed: bool = False):
             [float(v) for v in q["p0"]])
 
 
-def node_table(use_printed: bool = False):
+def node_table(use_printed: bool = False, shells=None):
     """Per-population arrays (length 48, index 4*d + j).
 
     Returns dict with integer hops cx, cy, the opposite index, the weight w_i,
-    and the node momentum p_i = p0_j (1, n_d/||n_d||).
+    and the node momentum p_i = p0_j (1, n_d/||n_d||).  shells = (w1, w2, p0)
+    replaces the paper's quadrature by another member of its family.
     """
-    w1, w2, p0 = shell_tables(use_printed)
+    w1, w2, p0 = shell_tables(use_printed) if shells is None else ([float(v) for v in x] for x in shells)
     cx, cy, opp, w, pt, pxx, pyy = [], [], [], [], [], [], []
     for d in range(NDIR):
         ex, ey = DIRECTIONS[d]

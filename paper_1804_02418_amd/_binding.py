@@ -10,7 +10,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librlbm.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 F64, F32, F16DEV = 0, 1, 2
 STORAGE = {"f64": F64, "f32": F32, "f16dev": F16DEV, F64: F64, F32: F32, F16DEV: F16DEV}
 EDGE = {"bottom": 0, "top": 1, "left": 2, "right": 3}
@@ -64,6 +64,12 @@ SIGNATURES = {
     "rlbm_set_tau": ([_vp, ctypes.c_double], None),
     "rlbm_set_drive": ([_vp, ctypes.c_double, ctypes.c_double], None),
     "rlbm_set_lca": ([_vp, ctypes.c_double], None),
+    "rlbm_set_quadrature": ([_vp, _dp, _dp, _dp], None),
+    "rlbm_mj_moment": ([ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp], None),
+    "rlbm_quadrature_massive": ([ctypes.c_double, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp],
+                                None),
+    "rlbm_quadrature_massless": ([ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_uint64,
+                                  ctypes.c_int, _dp, _dp, _dp, _dp], None),
     "rlbm_set_block_order": ([_vp, ctypes.c_int], None),
     "rlbm_batch_set_block_order": ([_vp, ctypes.c_int], None),
     "rlbm_set_reference": ([_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double], None),
@@ -213,6 +219,11 @@ class Lattice:
 
     def set_block_order(self, xcd_contiguous: bool):
         check(lib().rlbm_set_block_order(self._h, int(bool(xcd_contiguous))))
+
+    def set_quadrature(self, w1, w2, p0):
+        """Another member of the massless third-order quadrature family (then init again)."""
+        a = [np.ascontiguousarray(v, dtype=np.float64) for v in (w1, w2, p0)]
+        check(lib().rlbm_set_quadrature(self._h, *[x.ctypes.data_as(_dp) for x in a]))
 
     def set_lca(self, cg):
         """Local-capacitance force with capacitance C_g (None or inf: off)."""
@@ -387,6 +398,63 @@ class Batch:
         n = _i64()
         check(lib().rlbm_batch_sites(self._h, ctypes.byref(n)))
         return n.value
+
+
+class NotFound(RlbmError):
+    pass
+
+
+def mj_moment(mbar: float, a: int, b: int, c: int) -> float:
+    """<p0^a px^b py^c> of the rest Maxwell-Juttner weight (include/rlbm_quadrature.h)."""
+    v = ctypes.c_double()
+    check(lib().rlbm_mj_moment(float(mbar), int(a), int(b), int(c), ctypes.byref(v)))
+    return v.value
+
+
+def quadrature_massive(mbar: float, vectors, order: int = 3, nscan: int = 0):
+    """Search of Sec. 2.3 for massive particles: (v0, per-node weights,
+    smallest weight, residual).  Raises NotFound (carrying the best attempt
+    in .result) when no v0 gives non-negative weights."""
+    vec = np.ascontiguousarray(np.asarray(vectors, dtype=np.int32).reshape(-1, 2))
+    n = vec.shape[0]
+    w = np.zeros(n)
+    v0, mw, res = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    st = lib().rlbm_quadrature_massive(float(mbar), int(order), vec.ctypes.data, n, int(nscan), ctypes.byref(v0),
+                                       w.ctypes.data_as(_dp), ctypes.byref(mw), ctypes.byref(res))
+    out = (v0.value, w, mw.value, res.value)
+    if st == ENOTFOUND:
+        e = NotFound(st, lib().rlbm_last_error().decode(errors="replace"))
+        e.result = out
+        raise e
+    check(st)
+    return out
+
+
+def quadrature_massless(directions, nshells: int, order: int = 3, start=None, seed: int = 1, max_starts: int = 64):
+    """Search of Sec. 2.3 for massless particles: (p0[nshells] ascending,
+    weights[nshells, ndir], smallest weight, residual).  start = (p0, w) with
+    w shaped (nshells, ndir) starts from there instead of random starts."""
+    d = np.ascontiguousarray(np.asarray(directions, dtype=np.int32).reshape(-1, 2))
+    nd = d.shape[0]
+    p0 = np.zeros(nshells)
+    w = np.zeros((nshells, nd))
+    mw, res = ctypes.c_double(), ctypes.c_double()
+    sp = sw = None
+    if start is not None:
+        sp = np.ascontiguousarray(start[0], dtype=np.float64)
+        sw = np.ascontiguousarray(start[1], dtype=np.float64).reshape(nshells, nd)
+    st = lib().rlbm_quadrature_massless(int(order), d.ctypes.data, nd, int(nshells),
+                                        None if sp is None else sp.ctypes.data,
+                                        None if sw is None else sw.ctypes.data, int(seed), int(max_starts),
+                                        p0.ctypes.data_as(_dp), w.ctypes.data_as(_dp), ctypes.byref(mw),
+                                        ctypes.byref(res))
+    out = (p0, w, mw.value, res.value)
+    if st == ENOTFOUND:
+        e = NotFound(st, lib().rlbm_last_error().decode(errors="replace"))
+        e.result = out
+        raise e
+    check(st)
+    return out
 
 
 def _ptr(t):

@@ -570,6 +570,27 @@ rlbm_status rlbm_set_lca(rlbm_lattice *L, double inv_cg)
     return refresh(L, false);
 }
 
+rlbm_status rlbm_set_quadrature(rlbm_lattice *L, const double w1[4], const double w2[4], const double p0[4])
+{
+    CHECK_L(L);
+    if (!w1 || !w2 || !p0) return fail(RLBM_EINVAL, "rlbm_set_quadrature: NULL table");
+    Quadrature q;
+    for (int j = 0; j < 4; ++j) {
+        if (!(w1[j] >= 0) || !(w2[j] >= 0) || !(p0[j] > 0) || !std::isfinite(w1[j] + w2[j] + p0[j]))
+            return fail(RLBM_EINVAL, "rlbm_set_quadrature: weights must be >= 0 and energies > 0");
+        q.w1[j] = w1[j];
+        q.w2[j] = w2[j];
+        q.p0[j] = p0[j];
+    }
+    const double res = massless_stencil_residual(q);
+    if (!(res < 1e-12))
+        return fail(RLBM_EINVAL, "rlbm_set_quadrature: the orthonormality conditions fail by %.3g", res);
+    L->C.q = q;
+    L->initialized = false;
+    L->fields_valid = false;
+    return refresh(L, false);
+}
+
 rlbm_status rlbm_set_reference(rlbm_lattice *L, double n_ref, double T_ref, double scale)
 {
     CHECK_L(L);

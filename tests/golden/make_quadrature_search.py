@@ -16,6 +16,15 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 from oracle import quadrature_search as Q  # noqa: E402
 
 
+NL = chr(10)
+
+
+def mp_str(v):
+    import mpmath as mp
+
+    return mp.nstr(v, 20)
+
+
 def main():
     vec = Q.full_symmetric(Q.M5_ORBIT_REPS)
 
@@ -47,6 +56,23 @@ def main():
         for orb, wk in zip(orbs, w):
             fh.write(f"{orb[0][0]} {orb[0][1]} {len(orb)} {wk!r}\n")
     print("v0", v0, "min weight", min(w), "residual", res)
+
+    # another member of the massless family: the conditions solved from the
+    # printed values with the fourth shell moved from 0.9358 to 1.0
+    from oracle import quadrature as OQ
+
+    start = list(OQ.PRINTED_W1 + OQ.PRINTED_W2 + OQ.PRINTED_P0)
+    start[11] = "1.0"
+    sol = OQ.solve_from(tuple(start))
+    with open(os.path.join(HERE, "m0_family_member.txt"), "w") as fh:
+        fh.write("# A second massless third-order quadrature on the 48-node stencil (Sec. 2.3):" + NL)
+        fh.write("# the conditions solved (minimum-norm Gauss-Newton, 50 digits) from the printed" + NL)
+        fh.write("# values with p0_4 = 1.0.  Written by make_quadrature_search.py (oracle only)." + NL)
+        fh.write("# Rows: w1[4] (+-3,+-4)_FS, w2[4] (+-5,0)_FS, p0[4]; then the residual." + NL)
+        for key in ("w1", "w2", "p0"):
+            fh.write(" ".join(mp_str(v) for v in sol[key]) + NL)
+        fh.write(f"{sol['residual']:.3e}" + NL)
+    print("family member", [float(v) for v in sol["p0"]], "residual", sol["residual"])
 
 
 if __name__ == "__main__":

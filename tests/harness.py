@@ -8,7 +8,8 @@ import numpy as np
 def oracle_lattice(w, use_printed=False):
     import oracle
 
-    L = oracle.Lattice(oracle.stencil(use_printed), w["nx"], w["ny"], periodic_x=w["periodic_x"],
+    st = oracle.Stencil(shells=w["quadrature"]) if w.get("quadrature") is not None else oracle.stencil(use_printed)
+    L = oracle.Lattice(st, w["nx"], w["ny"], periodic_x=w["periodic_x"],
                        periodic_y=w["periodic_y"], contacts=w["contacts"], solid=w.get("mask"), tau=w["tau"],
                        F=w["F"], cg=w.get("cg"))
     i = w["init"]
@@ -20,6 +21,8 @@ def gpu_lattice(w, storage=None, shape=None):
     import paper_1804_02418_amd as rl
 
     L = rl.Lattice(w["nx"], w["ny"], storage or w.get("storage", "f64"))
+    if w.get("quadrature") is not None:
+        L.set_quadrature(*w["quadrature"])
     L.set_boundaries(w["periodic_x"], w["periodic_y"], w["contacts"])
     if w.get("mask") is not None:
         L.set_mask(w["mask"])

@@ -11,6 +11,10 @@
   solution (written by tests/golden/make_quadrature_search.py from the
   oracle) solves all conditions, is positive, and its v0 is where the
   smallest weight peaks (moving v0 by 1e-4 either way makes a weight negative).
+* The massless solutions form a family: a second member (stored by the same
+  script, solved from the printed values with the fourth shell moved to
+  1.0) satisfies every condition, has positive weights and differs from the
+  paper's quadrature.
 """
 import math
 
@@ -73,3 +77,19 @@ def test_m5_stencil_has_a_nonnegative_third_order_quadrature():
     # the window is narrow: a step of 1e-4 in v0 either way turns a weight negative
     for dv in (-1e-4, 1e-4):
         assert min(Q.orbit_weights_mp(mbar, v0 + dv, vec)[1]) < 0
+
+
+def read_family_member():
+    rows = read_golden("m0_family_member.txt")
+    w1, w2, p0 = ([float(v) for v in rows[k]] for k in range(3))
+    return w1, w2, p0
+
+
+def test_second_massless_family_member():
+    w1, w2, p0 = read_family_member()
+    t = OQ.node_table(shells=(w1, w2, p0))
+    w, q0, px, py = (np.asarray(t[k], dtype=np.float64) for k in ("w", "p0", "px", "py"))
+    assert Q.moment_residual(0.0, q0, px, py, w, order=3) < 1e-13
+    assert min(w1 + w2) > 0 and min(p0) > 0
+    ref = OQ.shell_tables()[2]
+    assert max(abs(a - b) for a, b in zip(p0, ref)) > 1e-3
