@@ -181,6 +181,9 @@ void fill_args(rlbm_lattice *L, StepArgs<R> &A)
     for (int r = 0; r < 4; ++r) A.aref_s[r] = R(A.a_ref[kRestK[r]] / L->scale);
     A.mask = L->mask;
     A.edge_contact = L->edge;
+    A.side_contacts = 0;
+    for (const rlbm_contact &k : L->contacts)
+        A.side_contacts |= k.edge == RLBM_EDGE_LEFT ? 1 : k.edge == RLBM_EDGE_RIGHT ? 2 : 0;
     A.gather_tab = L->gtab;
     A.nbnd = L->gtab_rows;
     A.contact_eta = static_cast<const R *>(L->contact_eta);
@@ -352,7 +355,7 @@ void tune_cache_store(const TuneKey &k, int tile)
 
 LaunchShape default_shape(int nx)
 {
-    int tx = ((nx - 2 * kReach + 63) / 64) * 64;
+    int tx = ((nx + 63) / 64) * 64;  // interior tiles span whole rows
     if (tx > 256) tx = 256;
     if (tx < 64) tx = 64;
     if (tx == 192) tx = 128;
@@ -905,7 +908,7 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
     double best = INFINITY;
     int best_tile = shape0.tile_x, best_nt = L->nt_store;
     const int nt0 = L->nt_store;
-    const int interior_w = L->nx - 2 * kReach;
+    const int interior_w = L->nx;  // interior tiles span whole rows
     for (int c = 0; c < 6 && e == hipSuccess; ++c) {
         const int tc = c % 3, nt = c / 3;
         if (ms_per_step) ms_per_step[c] = 0.0;
@@ -1002,6 +1005,7 @@ struct rlbm_batch {
     int *n_items = nullptr;
     int n_items_host = 0;
     int xcd = 0;  // XCD-contiguous item order
+    int nt = 0;   // streaming stores (every active sample has them on)
     double *part = nullptr;
     int part_blocks = 0;
     hipGraph_t graph = nullptr;
@@ -1041,6 +1045,7 @@ rlbm_status upload_descs_t(rlbm_batch *B)
     const int n = (int)B->lat.size();
     std::vector<BatchDesc<R>> d(n);
     std::vector<unsigned> items;
+    bool nt_all = true;
     for (int s = 0; s < n; ++s) {
         rlbm_lattice *L = B->lat[s];
         BatchDesc<R> &D = d[s];
@@ -1055,7 +1060,12 @@ rlbm_status upload_descs_t(rlbm_batch *B)
         D.parity_xor = L->cur;  // launches start at parity 0
         D.pad_ = 0;
         if (!B->active[s]) continue;
+        nt_all = nt_all && L->nt_store;
         for (int b = 0; b < nblk; ++b) items.push_back(((unsigned)s << kItemBlockBits) | (unsigned)b);
+    }
+    if ((nt_all ? 1 : 0) != B->nt) {
+        drop_graph(B);  // the captured graph holds the other store form
+        B->nt = nt_all ? 1 : 0;
     }
     HIP_TRY(hipMemcpyAsync(B->descs, d.data(), n * sizeof(BatchDesc<R>), hipMemcpyHostToDevice, B->stream));
     if (items.size() > B->items_cap) {
@@ -1085,7 +1095,7 @@ Store store_of(rlbm_storage st) { return st == RLBM_F64 ? Store::F64 : st == RLB
 rlbm_status batch_launch(rlbm_batch *B, int parity, int wf)
 {
     HIP_TRY(launch_batch_step(store_of(B->storage), B->descs, B->items, B->n_items, (int)B->items_cap, parity, wf,
-                              B->xcd, B->stream));
+                              B->xcd, B->nt, B->stream));
     return RLBM_OK;
 }
 
@@ -1362,7 +1372,7 @@ rlbm_status rlbm_batch_autotune(rlbm_batch *B, int trial_steps, double *ms_per_s
     for (int s = 0; s < n; ++s) nt0[s] = B->lat[s]->nt_store;
     for (int c = 0; c < 6 && st == RLBM_OK; ++c) {
         for (int s = 0; s < n; ++s) {
-            const int w = B->lat[s]->nx - 2 * kReach;
+            const int w = B->lat[s]->nx;
             int t = tiles[c % 3];
             while (t > 64 && t / 2 >= w) t /= 2;
             B->lat[s]->shape = LaunchShape{t, 256 / t};
@@ -1398,7 +1408,7 @@ rlbm_status rlbm_batch_autotune(rlbm_batch *B, int trial_steps, double *ms_per_s
             e = hipMemcpyAsync(L->prev, save + off[s] + pb + 4 * P * 8, 2 * P * 8, hipMemcpyDeviceToDevice, B->stream);
         if (e != hipSuccess && !st) st = fail(RLBM_EDEVICE, "rlbm_batch_autotune: restore: %s", hipGetErrorString(e));
         if (best_c >= 0) {
-            const int w = L->nx - 2 * kReach;
+            const int w = L->nx;
             int t = tiles[best_c % 3];
             while (t > 64 && t / 2 >= w) t /= 2;
             L->shape = LaunchShape{t, 256 / t};

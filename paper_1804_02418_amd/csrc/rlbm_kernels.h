@@ -59,36 +59,26 @@ constexpr int kMaxContacts = 16;
 constexpr unsigned kContactFlag = 0x80000000u;
 
 // Boundary part of the step grid: with an interior (nx, ny > 2 * reach, no
-// mask) the bottom and top bands of `reach` rows, then the left and right
-// bands of the rows in between; without one, every site.
+// mask) the bottom and top bands of `reach` rows (the side columns of the
+// rows in between belong to the interior tiles, which resolve their few
+// boundary populations in place); without one, every site.
 __host__ __device__ inline long long boundary_count(int nx, int ny, bool all)
 {
     if (all) return (long long)nx * ny;
-    return 2LL * kReach * nx + 2LL * kReach * (ny - 2 * kReach);
+    return 2LL * kReach * nx;
 }
 
 __host__ __device__ inline void boundary_site(long long idx, int nx, int ny, bool all, int &x, int &y)
 {
-    if (all) {
-        y = (int)(idx / nx);
-        x = (int)(idx - (long long)y * nx);
-        return;
-    }
     const long long band = (long long)kReach * nx;
-    if (idx < band) {
+    if (all || idx < band) {
         y = (int)(idx / nx);
         x = (int)(idx - (long long)y * nx);
-    } else if (idx < 2 * band) {
+    } else {
         const long long r = idx - band;
         const int ry = (int)(r / nx);
         y = ny - kReach + ry;
         x = (int)(r - (long long)ry * nx);
-    } else {
-        const long long r = idx - 2 * band;
-        const int ry = (int)(r / (2 * kReach));
-        y = kReach + ry;
-        const int c = (int)(r - (long long)ry * (2 * kReach));
-        x = c < kReach ? c : nx - 2 * kReach + c;
     }
 }
 
@@ -123,6 +113,7 @@ struct StepArgs {
     // boundaries
     const unsigned char *mask;        // nx*ny, 1 = solid (or null)
     const signed char *edge_contact;  // [bottom: nx][top: nx][left: ny][right: ny] -> contact or -1
+    int side_contacts;                // bit 0: the left edge has a contact span, bit 1: the right edge
     const R *contact_eta;             // [contact][48], eta units
     // boundary gather table [48][nbnd]: source element of population i of
     // boundary site b (plane offset included), or kContactFlag | (c*48 + i)
@@ -181,8 +172,9 @@ hipError_t launch_step(Store st, const void *args, const void *src, void *dst, L
 
 // Batched step: `grid` blocks (at least *n_items), block b taking work item
 // b, or xcd_block(b, grid) when `xcd` is set; blocks past *n_items leave.
+// nt: streaming population stores for every sample.
 hipError_t launch_batch_step(Store st, const void *descs, const unsigned *items, const int *n_items, int grid,
-                             int parity, int write_fields, int xcd, hipStream_t s);
+                             int parity, int write_fields, int xcd, int nt, hipStream_t s);
 // Per-sample residual partial sums (3 doubles per block, blocks_per_sample per sample).
 hipError_t launch_batch_residual(Store st, const void *descs, int nsamples, int blocks_per_sample, double *part,
                                  hipStream_t s);

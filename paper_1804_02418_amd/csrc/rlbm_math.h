@@ -186,12 +186,14 @@ RLBM_HD R harmonics_eval(const R H[kK], R p0, R t_cos, R t_sin)
     return ((q3 * p0 + q2) * p0 + q1) * p0 + q0;
 }
 
-// Appendix B: a^(k) for density n, temperature T and 4-velocity U, times
-// n/T, handed to sink(k, a_k) one coefficient at a time (so that a kernel can
-// convert each one as it is formed instead of holding all sixteen).
+// Appendix B: a^(k) for temperature T and 4-velocity U, times the density
+// factor sc = n/T, handed to sink(k, a_k) one coefficient at a time (so that
+// a kernel can convert each one as it is formed instead of holding all
+// sixteen).
 template <class Sink>
-RLBM_HD void appendix_b_each(double n, double T, double u0, double ux, double uy, Sink &&sink)
+RLBM_HD void appendix_b_each_sc(double sc, double T, double u0, double ux, double uy, Sink &&sink)
 {
+#pragma clang fp contract(on)
     const double s3 = 1.7320508075688772935274463;
     const double s15 = 3.8729833462074168851792654;
     const double s32 = 1.2247448713915890490986420;  // sqrt(3/2)
@@ -199,7 +201,6 @@ RLBM_HD void appendix_b_each(double n, double T, double u0, double ux, double uy
     const double Tu = T * u0 - 1.0;
     const double T2 = T * T;
     const double ux2 = ux * ux, u02 = u0 * u0;
-    const double sc = n / T;
     sink(0, sc);
     sink(1, sc * Tu);
     sink(2, sc * T * ux);
@@ -220,29 +221,44 @@ RLBM_HD void appendix_b_each(double n, double T, double u0, double ux, double uy
 
 RLBM_HD void appendix_b(double n, double T, double u0, double ux, double uy, double a[kK])
 {
-    appendix_b_each(n, T, u0, ux, uy, [&](int k, double v) { a[k] = v; });
+    appendix_b_each_sc(n / T, T, u0, ux, uy, [&](int k, double v) { a[k] = v; });
 }
+
+// Exact reciprocal and reciprocal square root (host callers; the kernels
+// pass hardware estimates refined by Newton steps).
+struct ExactRecip {
+    RLBM_HD double rcp(double x) const { return 1.0 / x; }
+    RLBM_HD double rsqrt(double x) const { return 1.0 / std::sqrt(x); }
+};
 
 // Landau frame of the contravariant stress-energy tensor (symmetric, entries
 // t00, t0x, t0y, txx, txy, tyy): eps U^a = T^ab U_b with U the timelike
 // eigenvector, U^0 > 0, U.U = 1.  eps is the largest real root of the
 // characteristic polynomial of M = T eta (eta = diag(1,-1,-1)), reached by
-// Newton's method from lambda = T^00 (an upper bound when the spatial
-// stresses are non-negative).  U is the cross product of the two spatial
-// rows of M - eps I, which carries no cancellation when the velocity is
-// small.  Returns false when no timelike eigenvector is found.
-RLBM_HD bool landau_frame(double t00, double t0x, double t0y, double txx, double txy, double tyy,
-                          double &eps, double &u0, double &ux, double &uy)
+// Newton's method from T^00 less its flow part (for a perfect fluid that
+// start lies between eps and T^00, so the iteration comes down to eps
+// monotonically, two steps near rest).  U is the cross product of the two
+// spatial rows of M - eps I, which carries no cancellation when the velocity
+// is small.  Returns false when no timelike eigenvector is found.
+template <class Ops = ExactRecip>
+RLBM_HD bool landau_frame(double t00, double t0x, double t0y, double txx, double txy, double tyy, double &eps,
+                          double &u0, double &ux, double &uy, const Ops &ops = Ops())
 {
+    // products fused within a statement only: the rounding is then fixed by
+    // the source, identical in every kernel that inlines this
+#pragma clang fp contract(on)
     const double c2 = t00 - txx - tyy;
     const double c1 = -t00 * txx + t0x * t0x - t00 * tyy + t0y * t0y + txx * tyy - txy * txy;
     // det of [[t00,-t0x,-t0y],[t0x,-txx,-txy],[t0y,-txy,-tyy]]
     const double c0 = t00 * (txx * tyy - txy * txy) + t0x * (txy * t0y - t0x * tyy) - t0y * (txx * t0y - t0x * txy);
-    double l = t00;
+    // start: a perfect fluid has t00 = (eps + P) g^2 - P and |t0| = (eps + P) g^2 v,
+    // so eps = t00 - |t0|^2 / (t00 + P) exactly; (txx + tyy) / 2 in place of P
+    // leaves an O(v^4) error on the high side
+    double l = t00 - fma(t0x, t0x, t0y * t0y) * ops.rcp(t00 + 0.5 * (txx + tyy));
     for (int it = 0; it < 64; ++it) {
         const double pl = ((l - c2) * l + c1) * l - c0;
         const double dp = (3.0 * l - 2.0 * c2) * l + c1;
-        const double step = pl / dp;
+        const double step = pl * ops.rcp(dp);
         l -= step;
         if (!(std::fabs(step) > 4.0 * 2.220446049250313e-16 * std::fabs(l))) break;
     }
@@ -256,7 +272,7 @@ RLBM_HD bool landau_frame(double t00, double t0x, double t0y, double txx, double
         u0 = ux = uy = NAN;
         return false;
     }
-    const double inv = 1.0 / std::sqrt(nn);
+    const double inv = ops.rsqrt(nn);
     u0 = v0 * inv;
     ux = vx * inv;
     uy = vy * inv;

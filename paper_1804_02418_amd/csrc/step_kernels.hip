@@ -67,6 +67,26 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *plane_at(T *base
     return (GT *)((GC *)base + site * (unsigned)sizeof(T));
 }
 
+// Reciprocal and reciprocal square root in float64 from the hardware
+// estimates (about 23 correct bits) and two Newton steps each, which leave
+// a few units in the last place: the Landau solve and the density factors
+// need no correctly rounded division.
+struct DeviceRecip {
+    __device__ double rcp(double x) const
+    {
+        double r = __builtin_amdgcn_rcp(x);
+        r = fma(fma(-x, r, 1.0), r, r);
+        return fma(fma(-x, r, 1.0), r, r);
+    }
+    __device__ double rsqrt(double x) const
+    {
+        const double h = 0.5 * x;
+        double r = __builtin_amdgcn_rsq(x);
+        r *= fma(-h * r, r, 1.5);
+        return r * fma(-h * r, r, 1.5);
+    }
+};
+
 // Discards the post-collision values (callers that read h afterwards).
 struct NoEmit {
     template <class R>
@@ -118,15 +138,18 @@ __device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, R
     const double nT = A.n_ref * A.T_ref;
     const double dN0 = A.n_ref + double(N0), dNx = double(Nx), dNy = double(Ny);
     double eps, u0, ux, uy;
+    const DeviceRecip rc;
     const bool ok = landau_frame(2.0 * nT + double(T00), double(T0x), double(T0y), nT + double(Txx), double(Txy),
-                                 nT + double(Tyy), eps, u0, ux, uy);
-    const double n = u0 * dN0 - ux * dNx - uy * dNy;
-    const double T = eps / (2.0 * n);
+                                 nT + double(Tyy), eps, u0, ux, uy, rc);
+    const double n = fma(u0, dN0, -fma(ux, dNx, uy * dNy));
+    // T = eps / (2 n) and the density factor n / T = 2 n^2 / eps
+    const double T = (0.5 * eps) * rc.rcp(n);
+    const double sc = (2.0 * n) * n * rc.rcp(eps);
     fields(SiteFields{n, u0, ux, uy, eps}, ok);
     const R U0 = R(u0 * A.tau_inv), Ux = R(ux * A.tau_inv), Uy = R(uy * A.tau_inv);
     // ---- equilibrium and force coefficients (deviation from the reference, / scale) ----
     R ad[kK];
-    appendix_b_each(n, T, u0, ux, uy, [&](int k, double v) { ad[k] = R((v - A.a_ref[k]) * A.inv_scale); });
+    appendix_b_each_sc(sc, T, u0, ux, uy, [&](int k, double v) { ad[k] = R((v - A.a_ref[k]) * A.inv_scale); });
     R Hb[kK];
     if (has_force) {
         // b = (Fx C_x + Fy C_y) a / scale with a / scale = ad + a_ref / scale,
@@ -284,11 +307,56 @@ __device__ __forceinline__ void gather_general(const StepArgs<R> &A, const S *__
     }
 }
 
+// Loads of a wave that holds side columns of an interior row (x < reach or
+// x >= nx - reach).  For a side lane, the populations whose source lies
+// beyond the left or right edge follow the boundary rules of the pull:
+// periodic wrap, else the edge's contact span, else bounce-back from the
+// site itself; every other lane and population pulls as in the interior.
+// The source row is always inside the lattice here.  Each load picks its
+// address per lane (no lane skips a load), and the contact equilibria, when
+// the side has contact spans at all, replace values afterwards.
+template <class S, class R>
+__device__ __forceinline__ void side_wave_gather(const StepArgs<R> &A, const S *__restrict__ src, int x, int y,
+                                                 unsigned site, R (&h)[kQ])
+{
+    const int nx = A.nx;
+    const long long P = A.plane;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int d = i / kShells;
+        const int sx = x - kCx[d];
+        long long e = (long long)i * P + (long long)(y - kCy[d]) * nx + sx;  // plain pull
+        if (kCx[d] != 0) {
+            const bool out = (unsigned)sx >= (unsigned)nx;
+            const long long wrapped = e + (sx < 0 ? nx : -nx);
+            const long long bounce = (long long)(kShells * ((d + kDirs / 2) % kDirs) + (i % kShells)) * P + site;
+            e = out ? (A.periodic_x ? wrapped : bounce) : e;
+        }
+        h[i] = StoreIO<S>::template load<R>(src + e);
+    }
+    if (!A.periodic_x && A.side_contacts) {
+#pragma unroll
+        for (int d = 0; d < kDirs; ++d) {
+            if (kCx[d] == 0) continue;
+            const int sx = x - kCx[d];
+            const bool out = (unsigned)sx >= (unsigned)nx;
+            const int c = out ? A.edge_contact[(sx < 0 ? 2 * nx : 2 * nx + A.ny) + (y - kCy[d])] : -1;
+            const int cc = c < 0 ? 0 : c;
+#pragma unroll
+            for (int j = 0; j < kShells; ++j) {
+                const R v = A.contact_eta[cc * kQ + kShells * d + j];
+                h[kShells * d + j] = c >= 0 ? v : h[kShells * d + j];
+            }
+        }
+    }
+}
+
 // One block of a time step.  The step's 1-D grid of 256-thread blocks: the
 // first nbnd blocks take the boundary sites (gather table or computed
-// gather), the rest tile the interior x in [5, nx - 5), y in [5, ny - 5)
+// gather), the rest tile the rows y in [5, ny - 5) over their whole width
 // with tile_x * rows sites per block, tiles aligned to tile_x so every
-// wavefront stores 64 aligned values.
+// wavefront stores 64 aligned values; the side columns of those rows patch
+// their boundary populations in place (side_gather).
 // Force mode of a step kernel, fixed at compile time so that no runtime
 // branch splits the register allocation: no force, the uniform drive, or
 // the drive plus the local-capacitance term.
@@ -300,7 +368,10 @@ enum ForceMode { kNoForce = 0, kDrive = 1, kLca = 2 };
 // is long code, kept out of the kernels that do not need it.
 enum GatherMode { kGatherTable = 0, kGatherComputed = 1, kGatherEither = 2 };
 
-template <class S, class R, int MODE, int GATHER>
+// NT: streaming (non-temporal) population stores.  A compile-time choice:
+// with a runtime flag the compiler merges the two store forms of each value
+// into one ordinary store.
+template <class S, class R, int MODE, int GATHER, bool NT>
 __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__restrict__ src, S *__restrict__ dst,
                                            int b, int nbnd, int tile_x, int tiles_x, int all, int wf)
 {
@@ -322,8 +393,13 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
         const int ty = t / tile_x;
         x = bx * tile_x + (t - ty * tile_x);
         y = kReach + by * rows + ty;
-        if (x < kReach || x >= nx - kReach || y >= A.ny - kReach) return;
+        if (x >= nx || y >= A.ny - kReach) return;
     }
+    const bool side = !bnd && (x < kReach || x >= nx - kReach);
+    // a wave's 64 lanes are consecutive sites of one row (tile_x is a
+    // multiple of 64): whether it touches a side column is uniform
+    const int x0 = x - (int)(threadIdx.x & 63);
+    const bool side_wave = !bnd && (x0 < kReach || x0 + 63 >= nx - kReach);
     const unsigned site = (unsigned)y * (unsigned)nx + (unsigned)x;
     if (bnd && A.has_mask && A.mask[site]) {
         if (wf) {
@@ -336,30 +412,39 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
     }
     // ---- force (before the gather: its temporaries die before h is loaded) ----
     R fx = A.fx, fy = A.fy;
-    if constexpr (MODE == kLca) lca_force(A, x, y, site, !bnd, fx, fy);
+    if constexpr (MODE == kLca) lca_force(A, x, y, site, !bnd && !side, fx, fy);
     // ---- gather ----
     R h[kQ];
     if (bnd) {
         const bool table = GATHER == kGatherTable || (GATHER == kGatherEither && A.gather_tab);
         if (table) {
-            // eight table codes, then their eight values, at a time: without
-            // the fence the compiler fetches all 48 codes first and the band's
-            // path alone would set the kernel's register budget
+            // eight table codes, then their eight values, at a time, the
+            // codes of the next eight already in flight: the band's path then
+            // waits for about four memory round trips instead of twelve, and
+            // holds at most sixteen codes (all 48 at once would set the
+            // kernel's register budget)
             const unsigned *__restrict__ tab = A.gather_tab;
+            unsigned c[2][8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) c[0][i] = tab[(long long)i * A.nbnd + idx];
 #pragma unroll
             for (int i0 = 0; i0 < kQ; i0 += 8) {
-                unsigned c[8];
+                const int cur = (i0 / 8) & 1;
+                if (i0 + 8 < kQ) {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) c[i] = tab[(long long)(i0 + i) * A.nbnd + idx];
+                    for (int i = 0; i < 8; ++i) c[cur ^ 1][i] = tab[(long long)(i0 + 8 + i) * A.nbnd + idx];
+                }
 #pragma unroll
                 for (int i = 0; i < 8; ++i)
-                    h[i0 + i] = (c[i] & kContactFlag) ? A.contact_eta[c[i] & ~kContactFlag]
-                                                      : StoreIO<S>::template load<R>(src + c[i]);
+                    h[i0 + i] = (c[cur][i] & kContactFlag) ? A.contact_eta[c[cur][i] & ~kContactFlag]
+                                                           : StoreIO<S>::template load<R>(src + c[cur][i]);
                 asm volatile("" ::: "memory");
             }
         } else if constexpr (GATHER != kGatherTable) {
             gather_general<S, R>(A, src, x, y, site, h);
         }
+    } else if (side_wave) {
+        side_wave_gather<S, R>(A, src, x, y, site, h);
     } else {
         // uniform plane base pointers + one 32-bit site offset
 #pragma unroll
@@ -372,10 +457,9 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
     // ---- collide; each post-collision value is stored as soon as it is
     // formed (streaming stores bypass the caches: the next step reads every
     // value once) ----
-    const bool nt = A.nt_store != 0;
     auto store = [&](int i, R v) {
         auto p = plane_at(dst + (long long)i * P, site);
-        if (nt)
+        if constexpr (NT)
             StoreIO<S>::template store_nt<R>(p, v);
         else
             StoreIO<S>::template store<R>(p, v);
@@ -390,13 +474,13 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
 // At most four waves per SIMD: measured on MI355X, the compiler's schedule
 // for that budget (about 110 VGPRs) beats the five-wave one (96 VGPRs) on
 // FP32 at 4096 x 2048 by 2% and is level elsewhere.
-template <class S, class R, int MODE, int GATHER>
+template <class S, class R, int MODE, int GATHER, bool NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void step_kernel(const StepArgs<R> A, const S *__restrict__ src,
                                                    S *__restrict__ dst, int nbnd, int tile_x, int tiles_x, int all,
                                                    int xcd)
 {
     const int b = xcd ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
-    step_block<S, R, MODE, GATHER>(A, src, dst, b, nbnd, tile_x, tiles_x, all, A.write_fields);
+    step_block<S, R, MODE, GATHER, NT>(A, src, dst, b, nbnd, tile_x, tiles_x, all, A.write_fields);
 }
 
 // Batched step: one block per work item of the list of (sample, block)
@@ -405,7 +489,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 // (A persistent grid looping over the items keeps each item's descriptor
 // live across iterations and needs every register of the SIMD, one wave
 // per SIMD; one item per block keeps the single-lattice kernel's budget.)
-template <class S, class R>
+template <class S, class R, bool NT>
 __global__ __launch_bounds__(256) void batch_step_kernel(const BatchDesc<R> *__restrict__ descs,
                                                          const unsigned *__restrict__ items,
                                                          const int *__restrict__ n_items_p, int parity, int wf,
@@ -419,7 +503,7 @@ __global__ __launch_bounds__(256) void batch_step_kernel(const BatchDesc<R> *__r
     const BatchDesc<R> &D = descs[smp];
     const int par = parity ^ D.parity_xor;
     // the drive variant serves every sample: a zero drive adds exactly zero
-    step_block<S, R, kDrive, kGatherEither>(D.a, static_cast<const S *>(D.pop[par]), static_cast<S *>(D.pop[par ^ 1]),
+    step_block<S, R, kDrive, kGatherEither, NT>(D.a, static_cast<const S *>(D.pop[par]), static_cast<S *>(D.pop[par ^ 1]),
                                             b, D.nbnd, D.tile_x, D.tiles_x, D.all, wf);
 }
 
@@ -601,9 +685,15 @@ hipError_t launch_step_t(const void *args, const void *src, void *dst, LaunchSha
     const int all = interior ? 0 : 1;
     const int mode = A.n_prev ? kLca : A.has_force ? kDrive : kNoForce;
     const int gather = A.gather_tab ? kGatherTable : kGatherComputed;
-#define RLBM_LAUNCH_STEP(M, G)                                                                                   \
-    hipLaunchKernelGGL((step_kernel<S, R, M, G>), grid, dim3(block), 0, s, A, in, out, nbnd, sh.tile_x, tiles_x, \
-                       all, sh.xcd)
+#define RLBM_LAUNCH_STEP(M, G)                                                                                     \
+    do {                                                                                                           \
+        if (A.nt_store)                                                                                            \
+            hipLaunchKernelGGL((step_kernel<S, R, M, G, true>), grid, dim3(block), 0, s, A, in, out, nbnd,         \
+                               sh.tile_x, tiles_x, all, sh.xcd);                                                   \
+        else                                                                                                       \
+            hipLaunchKernelGGL((step_kernel<S, R, M, G, false>), grid, dim3(block), 0, s, A, in, out, nbnd,        \
+                               sh.tile_x, tiles_x, all, sh.xcd);                                                   \
+    } while (0)
     if (gather == kGatherTable) {
         if (mode == kLca) RLBM_LAUNCH_STEP(kLca, kGatherTable);
         else if (mode == kDrive) RLBM_LAUNCH_STEP(kDrive, kGatherTable);
@@ -633,23 +723,30 @@ hipError_t launch_init_t(const void *args, const double *n, const double *T, con
 
 template <class S, class R>
 hipError_t launch_batch_t(const void *descs, const unsigned *items, const int *n_items, int grid, int parity, int wf,
-                          int xcd, hipStream_t s)
+                          int xcd, int nt, hipStream_t s)
 {
-    hipLaunchKernelGGL((batch_step_kernel<S, R>), dim3(grid), dim3(256), 0, s,
-                       static_cast<const BatchDesc<R> *>(descs), items, n_items, parity, wf, xcd);
+    if (nt)
+        hipLaunchKernelGGL((batch_step_kernel<S, R, true>), dim3(grid), dim3(256), 0, s,
+                           static_cast<const BatchDesc<R> *>(descs), items, n_items, parity, wf, xcd);
+    else
+        hipLaunchKernelGGL((batch_step_kernel<S, R, false>), dim3(grid), dim3(256), 0, s,
+                           static_cast<const BatchDesc<R> *>(descs), items, n_items, parity, wf, xcd);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_batch_step(Store st, const void *descs, const unsigned *items, const int *n_items, int grid,
-                             int parity, int write_fields, int xcd, hipStream_t s)
+                             int parity, int write_fields, int xcd, int nt, hipStream_t s)
 {
     if (grid <= 0) return hipErrorInvalidValue;
     switch (st) {
-    case Store::F64: return launch_batch_t<double, double>(descs, items, n_items, grid, parity, write_fields, xcd, s);
-    case Store::F32: return launch_batch_t<float, float>(descs, items, n_items, grid, parity, write_fields, xcd, s);
-    case Store::F16: return launch_batch_t<_Float16, float>(descs, items, n_items, grid, parity, write_fields, xcd, s);
+    case Store::F64:
+        return launch_batch_t<double, double>(descs, items, n_items, grid, parity, write_fields, xcd, nt, s);
+    case Store::F32:
+        return launch_batch_t<float, float>(descs, items, n_items, grid, parity, write_fields, xcd, nt, s);
+    case Store::F16:
+        return launch_batch_t<_Float16, float>(descs, items, n_items, grid, parity, write_fields, xcd, nt, s);
     }
     return hipErrorInvalidValue;
 }
