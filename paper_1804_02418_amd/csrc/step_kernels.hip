@@ -434,10 +434,26 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
 #pragma unroll
                     for (int i = 0; i < 8; ++i) c[cur ^ 1][i] = tab[(long long)(i0 + 8 + i) * A.nbnd + idx];
                 }
+                // every lane loads a population (code 0 stands in for a
+                // contact, an always valid element) and the contact
+                // equilibria are patched in only by waves that have one:
+                // a branch per value would make every 16-bit load wait for
+                // the one before it
+                bool any = false;
 #pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    h[i0 + i] = (c[cur][i] & kContactFlag) ? A.contact_eta[c[cur][i] & ~kContactFlag]
-                                                           : StoreIO<S>::template load<R>(src + c[cur][i]);
+                for (int i = 0; i < 8; ++i) {
+                    const unsigned code = c[cur][i];
+                    const bool contact = (code & kContactFlag) != 0;
+                    h[i0 + i] = StoreIO<S>::template load<R>(src + (contact ? 0u : code));
+                    any = any || contact;
+                }
+                if (__ballot(any)) {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const unsigned code = c[cur][i];
+                        if (code & kContactFlag) h[i0 + i] = A.contact_eta[code & ~kContactFlag];
+                    }
+                }
                 asm volatile("" ::: "memory");
             }
         } else if constexpr (GATHER != kGatherTable) {
