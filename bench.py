@@ -337,7 +337,8 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-sample batched-kernel throughput")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate network throughput")
     ap.add_argument("--surrogate-only", action="store_true", help="only time the surrogate network")
-    ap.add_argument("--variants", action="store_true", help="also time the other storages and 4096x2048")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the other storages at this size and the three storages at 4096x2048")
     ap.add_argument("--copy-bytes", type=int, default=0, help="only run the copy-bandwidth calibration")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch shape")
     args = ap.parse_args(argv)
@@ -383,16 +384,24 @@ def main(argv=None):
                      "traffic": measured_traffic(f"step_{args.storage}_{w['nx']}x{w['ny']}", sites)},
         "residual_last_call": resid,
     }
-    if args.variants:
+    if not args.no_variants:
+        # the same step at the other storages, and the 4096 x 2048 sample (the
+        # populations no longer fit the 256 MB Infinity Cache) at all three
         extra = {}
+
+        def variant(wv, st, steps, warmup):
+            s2, l2, _ = run_gpu(wv, st, steps, warmup)
+            n = wv["nx"] * wv["ny"]
+            gbs = 2 * 48 * BYTES_PER_POP[st] * n / (l2 / 1e3) / 1e9
+            extra[f"{wv['name']}_{st}"] = {"mlups": round(n * steps / s2 / 1e6, 1), "hbm_gbs": round(gbs, 1),
+                                           "frac": round(gbs / PEAK_HBM_GBS, 4)}
+
         for st in ("f64", "f16dev"):
-            s2, l2, _ = run_gpu(w, st, 2000, 100)
-            extra[f"{w['name']}_{st}"] = round(sites * 2000 / s2 / 1e6, 1)
+            variant(w, st, 2000, 100)
         big = workloads.graphene_sample(4096, 2048)
         for st in ("f64", "f32", "f16dev"):
-            s3, l3, _ = run_gpu(big, st, 200, 20)
-            extra[f"{big['name']}_{st}"] = round(4096 * 2048 * 200 / s3 / 1e6, 1)
-        out["variants_mlups"] = extra
+            variant(big, st, 200, 20)
+        out["variants"] = extra
     if not args.no_batch:
         out["batch_256"] = batch_throughput(args.storage)
     if not args.no_surrogate:
