@@ -74,7 +74,9 @@ rlbm_status rlbm_unet_adam_step(rlbm_unet *net, float lr, float beta1, float bet
  * building blocks of the network, exposed for testing and reuse):
  * y = act(conv(x, w) + b); dx = conv(dy, adjoint(w)); gw += sum dy (x) x.
  * x: B x H x W x ci, w: co x 3 x 3 x ci, y/dy: B x H x W x co (all BF16);
- * b, gw, gb: FP32.  ci, co multiples of 16.  stream may be NULL. */
+ * b, gw, gb: FP32.  ci, co multiples of 16; the BF16 tensors must start on
+ * 16-byte boundaries (the kernels move 8 channels per access), else
+ * RLBM_EINVAL.  stream may be NULL. */
 rlbm_status rlbm_conv3x3_forward(const void *x, const void *w, const float *b, void *y, int B, int H, int W, int ci,
                                  int co, int relu, void *hip_stream);
 rlbm_status rlbm_conv3x3_backward_data(const void *dy, const void *w, void *dx, int B, int H, int W, int ci, int co,

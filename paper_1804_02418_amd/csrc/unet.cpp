@@ -161,11 +161,10 @@ rlbm_status conv_bwd(rlbm_unet *N, int i, int B, bool want_input)
 {
     const Layer &l = N->L[i];
     const int h = N->lh(l.level), w = N->lw(l.level);
-    const long long n = (long long)B * h * w * l.co;
-    UTRY(relu_backward(N->gact[i], N->act[i], n, N->stream));
+    UTRY(relu_backward_bias(N->gact[i], N->act[i], N->part, N->grad + l.boff, (long long)B * h * w, l.co,
+                            N->stream));
     UTRY(conv3x3_backward_weight(N->gact[i], layer_input(N, i), N->part, N->grad + l.woff, B, h, w, l.ci, l.co,
                                  N->stream));
-    UTRY(channel_sum(N->gact[i], N->grad + l.boff, (long long)B * h * w, l.co, N->stream));
     if (want_input) {
         const char *wbf = static_cast<const char *>(N->theta_bf) + 2 * l.woff;
         UTRY(conv3x3_adjoint_weights(wbf, N->wt, l.ci, l.co, N->stream));
@@ -173,6 +172,15 @@ rlbm_status conv_bwd(rlbm_unet *N, int i, int B, bool want_input)
                              N->stream));
     }
     return RLBM_OK;
+}
+
+}  // namespace
+
+namespace {
+// The kernels read and write BF16 tensors 16 bytes (8 channels) at a time.
+bool misaligned16(const void *a, const void *b, const void *c)
+{
+    return ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) | reinterpret_cast<uintptr_t>(c)) & 15) != 0;
 }
 
 }  // namespace
@@ -241,11 +249,12 @@ rlbm_status rlbm_unet_create(int base, int cin, int cout, int height, int width,
     for (int i = 0; i < NLAYER; ++i) {
         const Layer &l = N->L[i];
         wt_max = std::max(wt_max, (size_t)l.co * 9 * l.ci);
-        if (l.k == 3) {
-            const long long np = (long long)px(N, l.level, max_batch);
-            const long long chunk = conv3x3_wgrad_chunk(np);
-            part_max = std::max(part_max, (size_t)((np + chunk - 1) / chunk) * l.co * 9 * l.ci);
-        }
+        const long long np = (long long)px(N, l.level, max_batch);
+        if (l.k == 3)
+            part_max = std::max(part_max, (size_t)conv3x3_wgrad_chunks(max_batch, N->lh(l.level), N->lw(l.level), l.ci, l.co) *
+                                              l.co * 9 * l.ci);
+        // bias sums (and the head's parameter sums): one row per block
+        part_max = std::max(part_max, (size_t)channel_sum_blocks(np) * l.co * (l.k == 3 ? 1 : l.ci + 1));
         alloc(&N->act[i], px(N, l.level, max_batch) * l.co * 2);
         alloc(&N->gact[i], px(N, l.level, max_batch) * l.co * 2);
     }
@@ -379,7 +388,7 @@ rlbm_status rlbm_unet_backward(rlbm_unet *N, const float *dy, int batch, float *
     const int B = batch;
     const int c0 = N->base, c1 = 2 * c0, c2 = 4 * c0, c3 = 8 * c0;
     const Layer &h = N->L[HEAD];
-    UTRY(head_backward(dy, N->act[D1B], static_cast<const char *>(N->theta_bf) + 2 * h.woff, N->gact[D1B],
+    UTRY(head_backward(dy, N->act[D1B], static_cast<const char *>(N->theta_bf) + 2 * h.woff, N->gact[D1B], N->part,
                        N->grad + h.woff, N->grad + h.boff, (long long)px(N, 0, B), h.ci, h.co, N->stream));
     rlbm_status st;
     auto block = [&](int a, int b, bool input) {
@@ -420,7 +429,7 @@ rlbm_status rlbm_unet_adam_step(rlbm_unet *N, float lr, float b1, float b2, floa
 rlbm_status rlbm_conv3x3_forward(const void *x, const void *w, const float *b, void *y, int B, int H, int W, int ci,
                                  int co, int relu, void *stream)
 {
-    if (!x || !w || !y || ci % 16 || co % 16 || B < 1 || H < 1 || W < 1)
+    if (!x || !w || !y || ci % 16 || co % 16 || B < 1 || H < 1 || W < 1 || misaligned16(x, w, y))
         return set_error(RLBM_EINVAL, "rlbm_conv3x3_forward: bad argument");
     UTRY(conv3x3_forward(x, w, b, y, B, H, W, ci, co, relu != 0, static_cast<hipStream_t>(stream)));
     return RLBM_OK;
@@ -429,7 +438,7 @@ rlbm_status rlbm_conv3x3_forward(const void *x, const void *w, const float *b, v
 rlbm_status rlbm_conv3x3_backward_data(const void *dy, const void *w, void *dx, int B, int H, int W, int ci, int co,
                                        void *stream)
 {
-    if (!dy || !w || !dx || ci % 16 || co % 16 || B < 1 || H < 1 || W < 1)
+    if (!dy || !w || !dx || ci % 16 || co % 16 || B < 1 || H < 1 || W < 1 || misaligned16(dy, w, dx))
         return set_error(RLBM_EINVAL, "rlbm_conv3x3_backward_data: bad argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
     void *wt = nullptr;
@@ -445,15 +454,15 @@ rlbm_status rlbm_conv3x3_backward_data(const void *dy, const void *w, void *dx, 
 rlbm_status rlbm_conv3x3_backward_weight(const void *dy, const void *x, float *gw, float *gb, int B, int H, int W,
                                          int ci, int co, void *stream)
 {
-    if (!dy || !x || !gw || ci % 16 || co % 16 || B < 1 || H < 1 || W < 1)
+    if (!dy || !x || !gw || ci % 16 || co % 16 || B < 1 || H < 1 || W < 1 || misaligned16(dy, x, x))
         return set_error(RLBM_EINVAL, "rlbm_conv3x3_backward_weight: bad argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const long long np = (long long)B * H * W;
-    const long long chunk = conv3x3_wgrad_chunk(np);
     float *part = nullptr;
-    UTRY(hipMalloc((void **)&part, (size_t)((np + chunk - 1) / chunk) * co * 9 * ci * 4));
+    const size_t nw = (size_t)conv3x3_wgrad_chunks(B, H, W, ci, co) * co * 9 * ci, nbias = (size_t)channel_sum_blocks(np) * co;
+    UTRY(hipMalloc((void **)&part, std::max(nw, nbias) * 4));
     hipError_t e = conv3x3_backward_weight(dy, x, part, gw, B, H, W, ci, co, s);
-    if (e == hipSuccess && gb) e = channel_sum(dy, gb, np, co, s);
+    if (e == hipSuccess && gb) e = channel_sum(dy, part, gb, np, co, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     ufree(part);
     if (e != hipSuccess) return set_error(RLBM_EDEVICE, hipGetErrorString(e));

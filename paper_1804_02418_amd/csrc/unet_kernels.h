@@ -12,15 +12,24 @@ hipError_t conv3x3_forward(const void *in, const void *w, const float *bias, voi
 // wt[ci][8 - tap][co] = w[co][tap][ci]; the gradient with respect to the input of a 3x3
 // convolution is conv3x3_forward(dout, wt) (no bias, no activation).
 hipError_t conv3x3_adjoint_weights(const void *w, void *wt, int Ci, int Co, hipStream_t s);
-// Pixels per weight-gradient partial; part needs ceil(B*H*W / chunk) * Co * 9 * Ci floats.
-long long conv3x3_wgrad_chunk(long long npix);
+// Weight-gradient partials (chunks of whole image rows); part needs
+// conv3x3_wgrad_chunks(B, H, W, Ci, Co) * Co * 9 * Ci floats.
+int conv3x3_wgrad_chunks(int B, int H, int W, int Ci, int Co);
 // gw[co][tap][ci] += sum_p dpre[p][co] * in[p + tap][ci] (deterministic two-pass reduction through part).
 hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part, float *gw, int B, int H, int W,
                                    int Ci, int Co, hipStream_t s);
-// gb[c] += sum_p d[p][c]
-hipError_t channel_sum(const void *d, float *gb, long long npix, int C, hipStream_t s);
+// Blocks of the per-channel and head-gradient sums: part needs
+// channel_sum_blocks(npix) * C floats (head_backward: * O * (C + 1)).
+constexpr int kSumBlocks = 1024;
+int channel_sum_blocks(long long npix);
+// gb[c] += sum_p d[p][c] (deterministic two-pass sum through part when C
+// divides 256, one block per channel otherwise)
+hipError_t channel_sum(const void *d, float *part, float *gb, long long npix, int C, hipStream_t s);
 // d *= (out > 0)
 hipError_t relu_backward(void *d, const void *out, long long n, hipStream_t s);
+// d *= (out > 0) over npix x C and gb[c] += sum_p d[p][c], in one pass when
+// C % 8 == 0 and C / 8 divides 256 (part as for channel_sum)
+hipError_t relu_backward_bias(void *d, const void *out, float *part, float *gb, long long npix, int C, hipStream_t s);
 hipError_t pool_forward(const void *in, void *out, int B, int H, int W, int C, hipStream_t s);
 // dx = dy / 4 broadcast to 2x2 blocks (+ channels [skip_off, skip_off + C) of skip, a B*H*W*skip_c tensor)
 hipError_t pool_backward(const void *dy, const void *skip, int skip_c, int skip_off, void *dx, int B, int H, int W,
@@ -29,8 +38,10 @@ hipError_t up_concat(const void *u, const void *skip, void *cat, int B, int H, i
 hipError_t up_backward(const void *dcat, void *du, int B, int H, int W, int Cu, int C, hipStream_t s);
 hipError_t head_forward(const void *x, const void *w, const float *b, float *y, long long npix, int C, int O,
                         hipStream_t s);
-hipError_t head_backward(const float *dy, const void *x, const void *w, void *dx, float *gw, float *gb, long long npix,
-                         int C, int O, hipStream_t s);
+// Head (1x1, C = 16 -> O = 3) backward: dx, and gw, gb += the parameter
+// gradients (deterministic two-pass sums through part).
+hipError_t head_backward(const float *dy, const void *x, const void *w, void *dx, float *part, float *gw, float *gb,
+                         long long npix, int C, int O, hipStream_t s);
 hipError_t mse(const float *y, const float *t, float *dy, double *part, int nblocks, long long n, hipStream_t s);
 hipError_t adam(float *theta, const float *g, float *m, float *v, void *theta_bf, long long n, float lr, float b1,
                 float b2, float eps, float c1, float c2, hipStream_t s);

@@ -14,6 +14,8 @@
 // i % 4.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "unet_kernels.h"
 
 namespace rlbm {
@@ -109,70 +111,172 @@ __global__ void conv3x3_adjoint_weights_kernel(const bf16 *__restrict__ w, bf16 
     }
 }
 
-// Weight gradient, one partial per pixel chunk:
+// Weight gradient, one partial per chunk of image rows:
 // part[chunk][co][tap][ci] = sum over the chunk's pixels p of
-//   dpre[p][co] * in[p shifted by tap][ci].
-// GEMM with M = co (16), N = ci (16), K = pixels (32 per step) for one tap.
-// grid.x = chunks, grid.y = ceil(ntiles / 4) with ntiles = (Co/16)*(Ci/16)*9.
+//   dpre[p][co] * in[p shifted by tap][ci]   (zero outside the image).
+// A GEMM with M = co, N = ci, K = pixels for each of the 9 taps.  The matrix
+// instructions want 8 consecutive pixels of one channel per lane, while
+// NHWC keeps channels contiguous, so each 32-pixel row segment is staged
+// through LDS transposed: As[co][px] (16 output channels) and, for 64 input
+// channels and the rows y-1, y, y+1, three copies Bs[dx + 1][ci][row][k]
+// already shifted by the tap's dx, so that every operand is one aligned
+// 16-byte LDS read.  Wavefront w owns input-channel tile w of the block and
+// keeps the 9 taps' 16 x 16 accumulators.
+// grid.x = chunks (kWgradRows rows each), grid.y = (Co / 16) * ceil(Ci / 64).
+constexpr int kWgradSeg = 32;
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restrict__ dpre,
                                                             const bf16 *__restrict__ in, float *__restrict__ part,
-                                                            int B, int H, int W, int Ci, int Co, int chunk_px)
+                                                            int B, int H, int W, int Ci, int Co, int rows_per_chunk)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int cot = Co / 16, cit = Ci / 16;
-    const int job = blockIdx.y * 4 + wave;
-    if (job >= cot * cit * 9) return;
-    const int tap = job % 9;
-    const int cg = (job / 9) % cit;
-    const int og = job / (9 * cit);
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    const long long total = (long long)B * H * W;
-    const long long p_begin = (long long)blockIdx.x * chunk_px;
-    const long long p_end = p_begin + chunk_px < total ? p_begin + chunk_px : total;
+    __shared__ __attribute__((aligned(16))) bf16 As[16][kWgradSeg];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[3][64][3][kWgradSeg];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int cib = (Ci + 63) / 64;
+    const int og = blockIdx.y / cib, cb = blockIdx.y % cib;
+    const int co0 = og * 16, ci0 = cb * 64;
+    const bool active = ci0 + 16 * wave < Ci;
     const int r = lane & 15, kq = lane >> 4;
-    const int co = og * 16 + r, ci = cg * 16 + r;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (long long p0 = p_begin; p0 < p_end; p0 += 32) {
-        bf16x8 a, bv;
+    const long long row0 = (long long)blockIdx.x * rows_per_chunk;
+    const long long rows_end = row0 + rows_per_chunk < (long long)B * H ? row0 + rows_per_chunk : (long long)B * H;
+    f32x4 acc[9];
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const long long p = p0 + kq * 8 + s;
-            bf16 av = (bf16)0.f, bb = (bf16)0.f;
-            if (p < p_end) {
-                av = dpre[p * Co + co];
-                const int x = (int)(p % W);
-                const long long rowid = p / W;
-                const int y = (int)(rowid % H);
-                const int yy = y + dy, xx = x + dx;
-                if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W)
-                    bb = in[(p + (long long)dy * W + dx) * Ci + ci];
+    for (int q = 0; q < 9; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16 z = (bf16)0.f;
+    for (long long gr = row0; gr < rows_end; ++gr) {
+        const int y = (int)(gr % H);
+        const long long img = gr / H;
+        for (int x0 = 0; x0 < W; x0 += kWgradSeg) {
+            const int seg = W - x0 < kWgradSeg ? W - x0 : kWgradSeg;
+            // ---- stage dpre: 32 pixels x 16 channels, two channels per thread
+            {
+                const int px = t >> 3, cp = (t & 7) * 2;
+                bf16 v0 = z, v1 = z;
+                if (px < seg) {
+                    const bf16 *q = dpre + ((img * H + y) * W + x0 + px) * Co + co0 + cp;
+                    v0 = q[0];
+                    v1 = q[1];
+                }
+                As[cp][px] = v0;
+                As[cp + 1][px] = v1;
             }
-            a[s] = av;
-            bv[s] = bb;
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc, 0, 0, 0);
-    }
-    // C[i = co row][j = ci col] in lane j + 16*(i/4), element i%4
-    const int jj = lane & 15;
-    float *o = part + (long long)blockIdx.x * Co * 9 * Ci;
+            // ---- stage in: rows y-1..y+1, pixels x0-1 .. x0+32, 64 channels in
+            // groups of 8; the value at pixel x0 + u serves tap dx at k = u - dx
+            for (int unit = t; unit < 3 * (kWgradSeg + 2) * 8; unit += 256) {
+                const int g = unit & 7, rest = unit >> 3;
+                const int u = rest % (kWgradSeg + 2) - 1, rr = rest / (kWgradSeg + 2);
+                const int yy = y + rr - 1, xx = x0 + u, c = ci0 + 8 * g;
+                bf16x8 v;
+                if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W && c < Ci)
+                    v = *reinterpret_cast<const bf16x8 *>(in + ((img * H + yy) * W + xx) * Ci + c);
+                else
+                    for (int e = 0; e < 8; ++e) v[e] = z;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int ii = 4 * (lane >> 4) + s;
-        o[((long long)(og * 16 + ii) * 9 + tap) * Ci + cg * 16 + jj] = acc[s];
+                for (int s2 = 0; s2 < 3; ++s2) {
+                    const int k = u + 1 - s2;
+                    if (k >= 0 && k < kWgradSeg) {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) Bs[s2][8 * g + e][rr][k] = v[e];
+                    }
+                }
+            }
+            __syncthreads();
+            if (active) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[r][kq * 8]);
+#pragma unroll
+                for (int tap = 0; tap < 9; ++tap) {
+                    const int dy = tap / 3, dx = tap % 3;
+                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[dx][16 * wave + r][dy][kq * 8]);
+                    acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[tap], 0, 0, 0);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (!active) return;
+    // C[i = co row][j = ci col] in lane j + 16*(i/4), element i%4
+    float *o = part + (long long)blockIdx.x * Co * 9 * Ci;
+    const int ci = ci0 + 16 * wave + (lane & 15);
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) {
+            const int co = co0 + 4 * (lane >> 4) + s2;
+            o[((long long)co * 9 + tap) * Ci + ci] = acc[tap][s2];
+        }
     }
 }
 
-// g[q] += sum over chunks of part[chunk][q] (fixed order: deterministic).
-__global__ void reduce_chunks_kernel(const float *__restrict__ part, float *__restrict__ g, long long n, int chunks)
+// g[q] += sum over chunks of part[chunk][q]: a block takes 16 entries q,
+// its 16 thread groups the chunks c = group (mod 16), and the 16 group sums
+// are added in group order (deterministic).
+__global__ __launch_bounds__(256) void reduce_chunks_kernel(const float *__restrict__ part, float *__restrict__ g,
+                                                            long long n, int chunks)
 {
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
-        float s = 0.f;
-        for (int c = 0; c < chunks; ++c) s += part[(long long)c * n + q];
-        g[q] += s;
+    const int qi = threadIdx.x & 15, grp = threadIdx.x >> 4;
+    const long long q = (long long)blockIdx.x * 16 + qi;
+    float s = 0.f;
+    if (q < n)
+        for (int c = grp; c < chunks; c += 16) s += part[(long long)c * n + q];
+    __shared__ float red[16][16];
+    red[grp][qi] = s;
+    __syncthreads();
+    if (grp == 0 && q < n) {
+        float t = 0.f;
+        for (int k = 0; k < 16; ++k) t += red[k][qi];
+        g[q] += t;
     }
 }
 
-// gb[c] += sum over pixels of d[p][c]; one block per channel.
+// Per-channel sums in two passes (deterministic: fixed partition, fixed
+// order), optionally fused with the ReLU gradient.  Pass 1: block b sums
+// the pixels of its chunk; thread t takes the eight channels 8 (t % G) ..
+// of pixels t / G, t / G + 256 / G, ... (G = C / 8 groups, one 16-byte
+// load each), applying d *= (out > 0) first when `out` is given; the block
+// adds up its 256 / G rows in a fixed tree and writes part[b][c].  Needs
+// C % 8 == 0 and G | 256.
+__global__ __launch_bounds__(256) void channel_sum_part_kernel(bf16 *__restrict__ d, const bf16 *__restrict__ out,
+                                                               float *__restrict__ part, long long npix, int C,
+                                                               long long chunk)
+{
+    const int t = threadIdx.x;
+    const int G = C / 8;
+    const int g = t % G, r = t / G, rows = 256 / G;
+    const long long p0 = (long long)blockIdx.x * chunk;
+    const long long p1 = p0 + chunk < npix ? p0 + chunk : npix;
+    float acc[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[e] = 0.f;
+    for (long long p = p0 + r; p < p1; p += rows) {
+        bf16x8 *q = reinterpret_cast<bf16x8 *>(d + p * C + 8 * g);
+        bf16x8 v = *q;
+        if (out) {
+            const bf16x8 o = *reinterpret_cast<const bf16x8 *>(out + p * C + 8 * g);
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (!((float)o[e] > 0.f)) v[e] = (bf16)0.f;
+            *q = v;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[e] += (float)v[e];
+    }
+    __shared__ float red[256][9];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[t][e] = acc[e];
+    __syncthreads();
+    for (int k = 128; k >= G; k >>= 1) {
+        if (t < k) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) red[t][e] += red[t + k][e];
+        }
+        __syncthreads();
+    }
+    if (t < G) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) part[(long long)blockIdx.x * C + 8 * t + e] = red[t][e];
+    }
+}
+
+// Fallback for channel counts that do not divide 256: one block per channel.
 __global__ __launch_bounds__(256) void channel_sum_kernel(const bf16 *__restrict__ d, float *__restrict__ gb,
                                                           long long npix, int C)
 {
@@ -187,6 +291,24 @@ __global__ __launch_bounds__(256) void channel_sum_kernel(const bf16 *__restrict
         __syncthreads();
     }
     if (threadIdx.x == 0) gb[c] += red[0];
+}
+
+// Pass 2: g[c] += sum over the nb blocks of part[b][c]; one block per
+// entry c, a fixed-shape tree over the blocks (deterministic).
+__global__ __launch_bounds__(256) void sum_parts_kernel(const float *__restrict__ part, float *__restrict__ g, int nb,
+                                                        int n)
+{
+    const int c = blockIdx.x;
+    float s = 0.f;
+    for (int b = threadIdx.x; b < nb; b += 256) s += part[(long long)b * n + c];
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) g[c] += red[0];
 }
 
 // d *= (out > 0): gradient through the ReLU of a layer with output `out`.
@@ -303,8 +425,8 @@ __global__ void head_bwd_data_kernel(const float *__restrict__ dy, const bf16 *_
     }
 }
 
-// Head parameter gradient: one block per output entry (o, c) of W (c < C)
-// or of the bias (c == C): gW[o][c] += sum_p dy[p][o] x[p][c], gb[o] += sum_p dy[p][o].
+// Head parameter gradient for other shapes: one block per output entry
+// (o, c) of W (c < C) or of the bias (c == C).
 __global__ __launch_bounds__(256) void head_wgrad_kernel(const float *__restrict__ dy, const bf16 *__restrict__ x,
                                                          float *__restrict__ gw, float *__restrict__ gb,
                                                          long long npix, int C, int O)
@@ -320,6 +442,73 @@ __global__ __launch_bounds__(256) void head_wgrad_kernel(const float *__restrict
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        if (c < C)
+            gw[o * C + c] += red[0];
+        else
+            gb[o] += red[0];
+    }
+}
+
+// Head parameter gradient, pass 1: block b covers a chunk of pixels, each
+// thread its pixels t, t + 256, ...; every thread keeps the O * (C + 1)
+// sums dy[p][o] x[p][c] (c < C) and dy[p][o] (the bias, c = C), the block
+// adds them up (wavefront shuffles, then across the four wavefronts) and
+// writes part[b][o * (C + 1) + c].  Pass 2 is sum_parts_kernel.
+template <int C, int O>
+__global__ __launch_bounds__(256) void head_wgrad_part_kernel(const float *__restrict__ dy, const bf16 *__restrict__ x,
+                                                              float *__restrict__ part, long long npix,
+                                                              long long chunk)
+{
+    constexpr int K = O * (C + 1);
+    float acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.f;
+    const long long p0 = (long long)blockIdx.x * chunk;
+    const long long p1 = p0 + chunk < npix ? p0 + chunk : npix;
+    for (long long p = p0 + threadIdx.x; p < p1; p += 256) {
+        float g[O], xv[C];
+#pragma unroll
+        for (int o = 0; o < O; ++o) g[o] = dy[p * O + o];
+#pragma unroll
+        for (int c = 0; c < C; ++c) xv[c] = (float)x[p * C + c];
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[o * (C + 1) + c] += g[o] * xv[c];
+            acc[o * (C + 1) + C] += g[o];
+        }
+    }
+    __shared__ float red[4][K];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        float v = acc[k];
+        for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+        if (lane == 0) red[wave][k] = v;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += 256)
+        part[(long long)blockIdx.x * K + k] = red[0][k] + red[1][k] + red[2][k] + red[3][k];
+}
+
+// Head parameter gradient, pass 2: gw[o][c] and gb[o] += the block sums of
+// part (rows of O * (C + 1) entries); one block per entry, a fixed tree.
+__global__ __launch_bounds__(256) void head_grad_scatter_kernel(const float *__restrict__ part, float *__restrict__ gw,
+                                                                float *__restrict__ gb, int nb, int C, int O)
+{
+    const int k = blockIdx.x;
+    const int K = O * (C + 1);
+    float s = 0.f;
+    for (int b = threadIdx.x; b < nb; b += 256) s += part[(long long)b * K + k];
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int m = 128; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int o = k / (C + 1), c = k % (C + 1);
         if (c < C)
             gw[o * C + c] += red[0];
         else
@@ -416,30 +605,75 @@ hipError_t conv3x3_adjoint_weights(const void *w, void *wt, int Ci, int Co, hipS
     return hipGetLastError();
 }
 
-long long conv3x3_wgrad_chunk(long long npix) { return npix < 4096 ? ((npix + 31) / 32) * 32 : 4096; }
+int conv3x3_wgrad_chunks(int B, int H, int W, int Ci, int Co)
+{
+    // about 1024 blocks in all (chunks x channel tiles), whole rows each
+    const long long rows = (long long)B * H;
+    const long long tiles = (long long)(Co / 16) * ((Ci + 63) / 64);
+    long long chunks = (1024 + tiles - 1) / tiles;
+    if (chunks > rows) chunks = rows;
+    if (chunks < 1) chunks = 1;
+    (void)W;
+    return (int)chunks;
+}
 
 hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part, float *gw, int B, int H, int W,
                                    int Ci, int Co, hipStream_t s)
 {
-    if (Ci % 16 || Co % 16) return hipErrorInvalidValue;
-    const long long npix = (long long)B * H * W;
-    const long long chunk = conv3x3_wgrad_chunk(npix);
-    const int chunks = (int)((npix + chunk - 1) / chunk);
-    const int jobs = (Co / 16) * (Ci / 16) * 9;
-    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(chunks, (jobs + 3) / 4), dim3(256), 0, s,
-                       static_cast<const bf16 *>(dpre), static_cast<const bf16 *>(in), part, B, H, W, Ci, Co,
-                       (int)chunk);
+    if (Ci % 16 || Co % 16 || B < 1 || H < 1 || W < 1) return hipErrorInvalidValue;
+    const int chunks = conv3x3_wgrad_chunks(B, H, W, Ci, Co);
+    const int per = (int)(((long long)B * H + chunks - 1) / chunks);
+    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(chunks, (Co / 16) * ((Ci + 63) / 64)), dim3(256), 0, s,
+                       static_cast<const bf16 *>(dpre), static_cast<const bf16 *>(in), part, B, H, W, Ci, Co, per);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long n = (long long)Co * 9 * Ci;
-    hipLaunchKernelGGL(reduce_chunks_kernel, dim3(grid_for(n)), dim3(256), 0, s, part, gw, n, chunks);
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, s, part, gw, n, chunks);
     return hipGetLastError();
 }
 
-hipError_t channel_sum(const void *d, float *gb, long long npix, int C, hipStream_t s)
+int channel_sum_blocks(long long npix)
 {
-    hipLaunchKernelGGL(channel_sum_kernel, dim3(C), dim3(256), 0, s, static_cast<const bf16 *>(d), gb, npix, C);
+    const long long b = (npix + 1023) / 1024;  // at least 1024 pixels per block
+    return (int)(b < kSumBlocks ? (b < 1 ? 1 : b) : kSumBlocks);
+}
+
+namespace {
+bool fast_sum_shape(int C) { return C >= 8 && C % 8 == 0 && C <= 2048 && 256 % (C / 8) == 0; }
+
+hipError_t sum_launch(bf16 *d, const bf16 *out, float *part, float *gb, long long npix, int C, hipStream_t s)
+{
+    const int nb = channel_sum_blocks(npix);
+    const long long chunk = (npix + nb - 1) / nb;
+    hipLaunchKernelGGL(channel_sum_part_kernel, dim3(nb), dim3(256), 0, s, d, out, part, npix, C, chunk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(C), dim3(256), 0, s, part, gb, nb, C);
     return hipGetLastError();
+}
+}  // namespace
+
+hipError_t channel_sum(const void *d, float *part, float *gb, long long npix, int C, hipStream_t s)
+{
+    if (C < 1 || npix < 1) return hipErrorInvalidValue;
+    if (!fast_sum_shape(C)) {
+        hipLaunchKernelGGL(channel_sum_kernel, dim3(C), dim3(256), 0, s, static_cast<const bf16 *>(d), gb, npix, C);
+        return hipGetLastError();
+    }
+    // no ReLU: the kernel only reads d
+    return sum_launch(static_cast<bf16 *>(const_cast<void *>(d)), nullptr, part, gb, npix, C, s);
+}
+
+hipError_t relu_backward_bias(void *d, const void *out, float *part, float *gb, long long npix, int C, hipStream_t s)
+{
+    if (C < 1 || npix < 1) return hipErrorInvalidValue;
+    if (!fast_sum_shape(C)) {
+        hipError_t e = relu_backward(d, out, npix * C, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(channel_sum_kernel, dim3(C), dim3(256), 0, s, static_cast<const bf16 *>(d), gb, npix, C);
+        return hipGetLastError();
+    }
+    return sum_launch(static_cast<bf16 *>(d), static_cast<const bf16 *>(out), part, gb, npix, C, s);
 }
 
 hipError_t relu_backward(void *d, const void *out, long long n, hipStream_t s)
@@ -488,15 +722,26 @@ hipError_t head_forward(const void *x, const void *w, const float *b, float *y, 
     return hipGetLastError();
 }
 
-hipError_t head_backward(const float *dy, const void *x, const void *w, void *dx, float *gw, float *gb, long long npix,
-                         int C, int O, hipStream_t s)
+hipError_t head_backward(const float *dy, const void *x, const void *w, void *dx, float *part, float *gw, float *gb,
+                         long long npix, int C, int O, hipStream_t s)
 {
+    if (C < 1 || O < 1 || npix < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(head_bwd_data_kernel, dim3(grid_for(npix * C)), dim3(256), 0, s, dy,
                        static_cast<const bf16 *>(w), static_cast<bf16 *>(dx), npix, C, O);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(head_wgrad_kernel, dim3(O * (C + 1)), dim3(256), 0, s, dy, static_cast<const bf16 *>(x), gw, gb,
-                       npix, C, O);
+    if (C != 16 || O != 3) {
+        hipLaunchKernelGGL(head_wgrad_kernel, dim3(O * (C + 1)), dim3(256), 0, s, dy, static_cast<const bf16 *>(x), gw,
+                           gb, npix, C, O);
+        return hipGetLastError();
+    }
+    const int nb = channel_sum_blocks(npix);
+    const long long chunk = (npix + nb - 1) / nb;
+    hipLaunchKernelGGL((head_wgrad_part_kernel<16, 3>), dim3(nb), dim3(256), 0, s, dy, static_cast<const bf16 *>(x),
+                       part, npix, chunk);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(head_grad_scatter_kernel, dim3(O * (C + 1)), dim3(256), 0, s, part, gw, gb, nb, C, O);
     return hipGetLastError();
 }
 

@@ -3,7 +3,8 @@
 The FP64 path must match the oracle to 1e-12 relative (err_n) and to 1e-12
 of the run's largest velocity (err_u), element by element, on the same
 seeded inputs: the shear wave (500 steps), a ragged device with walls,
-contacts on three edges and a drive, a masked obstacle, tiny periodic
+contacts on three edges and a drive, contacts on all four edges, a masked
+obstacle, tiny periodic
 lattices whose hops wrap several times, and -- at the full 1024 x 512 size
 of the graphene sample -- one step from the GPU's own state computed by the
 oracle at every site.
@@ -71,6 +72,21 @@ def test_masked_obstacle_periodic_x_matches_oracle():
     mask[5:9, 100:128] = 1
     w["mask"] = mask
     _compare_run(w, [0, 1, 3, 60])
+
+
+@pytest.mark.parametrize("periodic_y", [False, True])
+def test_contacts_on_every_edge_match_oracle(periodic_y):
+    """Contact spans on all four edges, two of them reaching the corners: the
+    side columns of the interior rows (left and right contacts and walls,
+    resolved inside the row tiles) and the top and bottom bands (gather
+    table) both meet every boundary rule."""
+    w = workloads.small_device(nx=150, ny=60, steps=40)
+    c = w["contacts"]
+    w["contacts"] = [dict(c[0], edge="bottom", start=10, width=30), dict(c[2], edge="top", start=100, width=50),
+                     dict(c[3], edge="left", start=0, width=20), dict(c[1], edge="right", start=30, width=30)]
+    if periodic_y:
+        w.update(periodic_y=True, contacts=[k for k in w["contacts"] if k["edge"] in ("left", "right")])
+    _compare_run(w, [0, 1, 5, 40])
 
 
 @pytest.mark.parametrize("nx,ny", [(1, 6), (3, 7), (5, 2), (70, 3)])

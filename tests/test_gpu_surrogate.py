@@ -59,13 +59,15 @@ def test_conv3x3_forward_matches_reference(ci, co, relu):
     assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("ci,co", [(16, 32), (48, 16)])
-def test_conv3x3_backward_kernels_match_reference(ci, co):
+@pytest.mark.parametrize("ci,co,B,H,W", [(16, 32, 2, 16, 32), (48, 16, 2, 16, 32), (80, 32, 3, 20, 48),
+                                         (128, 16, 2, 160, 16)])
+def test_conv3x3_backward_kernels_match_reference(ci, co, B, H, W):
+    """Also partial 64-channel blocks, widths that are not a multiple of the
+    32-pixel segment, and several row chunks (320 rows of 16 pixels)."""
     import paper_1804_02418_amd as rl
 
     torch = _torch()
     rng = np.random.default_rng(7 + ci)
-    B, H, W = 2, 16, 32
     x = _bf16_round(rng.normal(size=(B, H, W, ci)))
     w = _bf16_round(rng.normal(size=(co, 3, 3, ci)) / np.sqrt(9 * ci))
     dy = _bf16_round(rng.normal(size=(B, H, W, co)))
