@@ -211,11 +211,13 @@ rlbm_status rlbm_get_state(rlbm_lattice *lat, void *dst, size_t bytes);
 rlbm_status rlbm_set_state(rlbm_lattice *lat, const void *src, size_t bytes);
 
 /* Work decomposition of the step kernel: each 256-thread block of the
- * lattice interior covers tile_x consecutive sites (64, 128 or 256: a
- * multiple of the 64-wide wavefront) of rows = 256 / tile_x rows.  Results do
- * not depend on it (every site is computed independently); only speed does.
- * Default: the largest of 64/128/256 not above the interior width rounded up
- * to 64. */
+ * lattice interior (the rows 5 .. ny-6 at full width, when the lattice has
+ * no solid mask and nx, ny > 10) covers tile_x consecutive sites (64, 128 or
+ * 256: a multiple of the 64-wide wavefront) of rows = 256 / tile_x rows; the
+ * top and bottom 5-row bands (every site, with a mask) run through a
+ * host-built gather table.  Results do not depend on it (every site is
+ * computed independently); only speed does.  Default: the largest of
+ * 64/128/256 not above the width rounded up to 64. */
 rlbm_status rlbm_set_launch_shape(rlbm_lattice *lat, int tile_x, int rows);
 
 /* Block order of the step kernel: xcd_contiguous = 1 deals each of the 8
@@ -225,11 +227,13 @@ rlbm_status rlbm_set_launch_shape(rlbm_lattice *lat, int tile_x, int rows);
  * blocks alternate between XCDs.  Results are identical either way. */
 rlbm_status rlbm_set_block_order(rlbm_lattice *lat, int xcd_contiguous);
 
-/* Streaming (non-temporal) stores of the populations: on = 1 makes the step
- * kernel's stores bypass the caches.  Pays off once the two population
- * arrays outgrow the 256 MB Infinity Cache (the default there); below it the
- * next step's reads hit the cache and ordinary stores are faster.  Results
- * are identical either way. */
+/* Streaming (non-temporal) stores of the populations: on = 1 launches the
+ * form of the step kernel whose stores bypass the caches.  Pays off once the
+ * two population arrays outgrow the 256 MB Infinity Cache (the default
+ * there; 12% faster at 4096 x 2048 in FP32); below it the next step's reads
+ * hit the cache and ordinary stores are faster (25% at 1024 x 512).  Results
+ * are identical either way.  Batches use the streaming form when every
+ * active sample has it on. */
 rlbm_status rlbm_set_streaming_stores(rlbm_lattice *lat, int on);
 
 /* Autotuner: time every candidate launch shape of the step kernel on this
@@ -266,7 +270,8 @@ typedef struct {
 /* Create a batch of nsamples (>= 1) lattices with one storage, all ordered
  * on one stream (hip_stream, or a stream the batch creates when NULL), and
  * initialise each to its uniform equilibrium.  The samples may differ in
- * size and parameters. */
+ * size and parameters.  When their populations together outgrow the 256 MB
+ * Infinity Cache, every sample starts with streaming stores on. */
 rlbm_status rlbm_batch_create(const rlbm_sample *samples, int nsamples, rlbm_storage storage, void *hip_stream,
                               rlbm_batch **out);
 

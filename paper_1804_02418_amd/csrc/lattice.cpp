@@ -1179,6 +1179,14 @@ rlbm_status rlbm_batch_create(const rlbm_sample *samples, int nsamples, rlbm_sto
         if (st) g_error = "sample " + std::to_string(s) + ": " + g_error;
     }
     B->active.assign(nsamples, 1);
+    if (!st) {
+        // the batch streams all its samples each step: once their populations
+        // together outgrow the 256 MB Infinity Cache, streaming stores by default
+        double bytes = 0.0;
+        for (rlbm_lattice *L : B->lat) bytes += 2.0 * (double)L->plane() * kQ * store_bytes(storage);
+        if (bytes > 256.0 * 1024 * 1024)
+            for (rlbm_lattice *L : B->lat) rlbm_set_streaming_stores(L, 1);
+    }
     const size_t desc_bytes = nsamples * (storage == RLBM_F64 ? sizeof(BatchDesc<double>) : sizeof(BatchDesc<float>));
     hipError_t e = hipSuccess;
     if (!st) e = hipMalloc(&B->descs, desc_bytes);
