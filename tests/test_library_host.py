@@ -78,3 +78,39 @@ def test_null_handle_is_rejected():
     assert rl.lib().rlbm_step(None, 1) == _binding.EINVAL
     assert rl.lib().rlbm_set_lca(None, 0.1) == _binding.EINVAL
     rl.lib().rlbm_destroy(None)
+
+
+@pytest.mark.parametrize("nx,ny,storage", [(65536, 8192, 0), (65536, 32769, 2)])
+def test_create_rejects_oversized_lattices(nx, ny, storage):
+    """A population plane must stay below 4 GiB (the kernels address each
+    plane with a 32-bit byte offset) and the site count below 2^31; both are
+    refused before any device call."""
+    import paper_1804_02418_amd as rl
+    from paper_1804_02418_amd import _binding
+
+    h = ctypes.c_void_p()
+    assert rl.lib().rlbm_create(nx, ny, storage, None, ctypes.byref(h)) == _binding.EINVAL
+    assert not h.value
+
+
+def test_conv_entry_points_reject_misaligned_tensors():
+    """The surrogate's convolution kernels move 8 BF16 channels (16 bytes)
+    per access: tensors that do not start on a 16-byte boundary are refused
+    on the host."""
+    import paper_1804_02418_amd as rl
+    from paper_1804_02418_amd import _binding
+
+    L = rl.lib()
+    good, bad = ctypes.c_void_p(1 << 20), ctypes.c_void_p((1 << 20) + 2)
+    assert L.rlbm_conv3x3_forward(bad, good, None, good, 1, 16, 16, 16, 16, 1, None) == _binding.EINVAL
+    assert L.rlbm_conv3x3_backward_data(good, good, bad, 1, 16, 16, 16, 16, None) == _binding.EINVAL
+    assert L.rlbm_conv3x3_backward_weight(bad, good, good, None, 1, 16, 16, 16, 16, None) == _binding.EINVAL
+    assert L.rlbm_conv3x3_backward_weight(good, good, good, None, 1, 16, 16, 24, 16, None) == _binding.EINVAL
+
+
+def test_store_form_and_block_order_reject_bad_arguments():
+    import paper_1804_02418_amd as rl
+    from paper_1804_02418_amd import _binding
+
+    assert rl.lib().rlbm_set_streaming_stores(None, 1) == _binding.EINVAL
+    assert rl.lib().rlbm_set_block_order(None, 0) == _binding.EINVAL
