@@ -116,25 +116,30 @@ __global__ void conv3x3_adjoint_weights_kernel(const bf16 *__restrict__ w, bf16 
 //   dpre[p][co] * in[p shifted by tap][ci]   (zero outside the image).
 // A GEMM with M = co, N = ci, K = pixels for each of the 9 taps.  The matrix
 // instructions want 8 consecutive pixels of one channel per lane, while
-// NHWC keeps channels contiguous, so each 32-pixel row segment is staged
-// through LDS transposed: As[co][px] (16 output channels) and, for 64 input
-// channels and the rows y-1, y, y+1, three copies Bs[dx + 1][ci][row][k]
-// already shifted by the tap's dx, so that every operand is one aligned
-// 16-byte LDS read.  Wavefront w owns input-channel tile w of the block and
-// keeps the 9 taps' 16 x 16 accumulators.
-// grid.x = chunks (kWgradRows rows each), grid.y = (Co / 16) * ceil(Ci / 64).
-constexpr int kWgradSeg = 32;
+// NHWC keeps channels contiguous, so each row segment of SEG pixels is
+// staged through LDS transposed: As[co][px] (16 output channels) and, for
+// CIB input channels and the rows y-1, y, y+1, three copies
+// Bs[dx + 1][ci][row][k] already shifted by the tap's dx, so that every
+// operand is one aligned 16-byte LDS read.  CIB * SEG = 2048 (64 x 32,
+// 32 x 64 or 16 x 128, by the input channel count): the four wavefronts
+// take CIB / 16 channel tiles times SEG / 32 pixel quarters, each keeps the
+// 9 taps' 16 x 16 accumulators, and the quarters of a tile are added in
+// order at the end.
+// grid.x = chunks (whole rows each), grid.y = (Co / 16) * ceil(Ci / CIB).
+template <int CIB>
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restrict__ dpre,
                                                             const bf16 *__restrict__ in, float *__restrict__ part,
                                                             int B, int H, int W, int Ci, int Co, int rows_per_chunk)
 {
-    __shared__ __attribute__((aligned(16))) bf16 As[16][kWgradSeg];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[3][64][3][kWgradSeg];
+    constexpr int SEG = 2048 / CIB, NCT = CIB / 16;
+    __shared__ __attribute__((aligned(16))) bf16 As[16][SEG];
+    __shared__ __attribute__((aligned(16))) bf16 Bs[3][CIB][3][SEG];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const int cib = (Ci + 63) / 64;
+    const int ct = wave % NCT, kp = wave / NCT;
+    const int cib = (Ci + CIB - 1) / CIB;
     const int og = blockIdx.y / cib, cb = blockIdx.y % cib;
-    const int co0 = og * 16, ci0 = cb * 64;
-    const bool active = ci0 + 16 * wave < Ci;
+    const int co0 = og * 16, ci0 = cb * CIB;
+    const bool active = ci0 + 16 * ct < Ci;
     const int r = lane & 15, kq = lane >> 4;
     const long long row0 = (long long)blockIdx.x * rows_per_chunk;
     const long long rows_end = row0 + rows_per_chunk < (long long)B * H ? row0 + rows_per_chunk : (long long)B * H;
@@ -145,11 +150,11 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
     for (long long gr = row0; gr < rows_end; ++gr) {
         const int y = (int)(gr % H);
         const long long img = gr / H;
-        for (int x0 = 0; x0 < W; x0 += kWgradSeg) {
-            const int seg = W - x0 < kWgradSeg ? W - x0 : kWgradSeg;
-            // ---- stage dpre: 32 pixels x 16 channels, two channels per thread
-            {
-                const int px = t >> 3, cp = (t & 7) * 2;
+        for (int x0 = 0; x0 < W; x0 += SEG) {
+            const int seg = W - x0 < SEG ? W - x0 : SEG;
+            // ---- stage dpre: SEG pixels x 16 channels, two channels per unit
+            for (int unit = t; unit < SEG * 8; unit += 256) {
+                const int px = unit >> 3, cp = (unit & 7) * 2;
                 bf16 v0 = z, v1 = z;
                 if (px < seg) {
                     const bf16 *q = dpre + ((img * H + y) * W + x0 + px) * Co + co0 + cp;
@@ -159,11 +164,11 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
                 As[cp][px] = v0;
                 As[cp + 1][px] = v1;
             }
-            // ---- stage in: rows y-1..y+1, pixels x0-1 .. x0+32, 64 channels in
-            // groups of 8; the value at pixel x0 + u serves tap dx at k = u - dx
-            for (int unit = t; unit < 3 * (kWgradSeg + 2) * 8; unit += 256) {
-                const int g = unit & 7, rest = unit >> 3;
-                const int u = rest % (kWgradSeg + 2) - 1, rr = rest / (kWgradSeg + 2);
+            // ---- stage in: rows y-1..y+1, pixels x0-1 .. x0+SEG, CIB channels
+            // in groups of 8; the value at pixel x0 + u serves tap dx at k = u - dx
+            for (int unit = t; unit < 3 * (SEG + 2) * (CIB / 8); unit += 256) {
+                const int g = unit % (CIB / 8), rest = unit / (CIB / 8);
+                const int u = rest % (SEG + 2) - 1, rr = rest / (SEG + 2);
                 const int yy = y + rr - 1, xx = x0 + u, c = ci0 + 8 * g;
                 bf16x8 v;
                 if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W && c < Ci)
@@ -173,35 +178,46 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
 #pragma unroll
                 for (int s2 = 0; s2 < 3; ++s2) {
                     const int k = u + 1 - s2;
-                    if (k >= 0 && k < kWgradSeg) {
+                    if (k >= 0 && k < SEG) {
 #pragma unroll
                         for (int e = 0; e < 8; ++e) Bs[s2][8 * g + e][rr][k] = v[e];
                     }
                 }
             }
             __syncthreads();
-            if (active) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[r][kq * 8]);
+            if (active && kp * 32 < seg) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[r][kp * 32 + kq * 8]);
 #pragma unroll
                 for (int tap = 0; tap < 9; ++tap) {
                     const int dy = tap / 3, dx = tap % 3;
-                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[dx][16 * wave + r][dy][kq * 8]);
+                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[dx][16 * ct + r][dy][kp * 32 + kq * 8]);
                     acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[tap], 0, 0, 0);
                 }
             }
             __syncthreads();
         }
     }
-    if (!active) return;
+    // add the pixel quarters of each channel tile in order, through LDS
+    float *red = reinterpret_cast<float *>(&Bs[0][0][0][0]);  // 4 x 9 x 4 x 64 floats = sizeof(Bs)
+    static_assert(sizeof(Bs) >= 4 * 9 * 4 * 64 * sizeof(float), "reduction space");
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) red[((wave * 9 + tap) * 4 + s2) * 64 + lane] = acc[tap][s2];
+    __syncthreads();
+    if (!active || kp != 0) return;
     // C[i = co row][j = ci col] in lane j + 16*(i/4), element i%4
     float *o = part + (long long)blockIdx.x * Co * 9 * Ci;
-    const int ci = ci0 + 16 * wave + (lane & 15);
+    const int ci = ci0 + 16 * ct + (lane & 15);
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
 #pragma unroll
         for (int s2 = 0; s2 < 4; ++s2) {
+            float v = 0.f;
+#pragma unroll
+            for (int q = 0; q < 4 / NCT; ++q) v += red[(((ct + q * NCT) * 9 + tap) * 4 + s2) * 64 + lane];
             const int co = co0 + 4 * (lane >> 4) + s2;
-            o[((long long)co * 9 + tap) * Ci + ci] = acc[tap][s2];
+            o[((long long)co * 9 + tap) * Ci + ci] = v;
         }
     }
 }
@@ -605,11 +621,17 @@ hipError_t conv3x3_adjoint_weights(const void *w, void *wt, int Ci, int Co, hipS
     return hipGetLastError();
 }
 
+namespace {
+// input channels staged per block of the weight gradient
+int wgrad_cib(int Ci) { return Ci == 16 ? 16 : Ci == 32 ? 32 : 64; }
+}  // namespace
+
 int conv3x3_wgrad_chunks(int B, int H, int W, int Ci, int Co)
 {
     // about 1024 blocks in all (chunks x channel tiles), whole rows each
     const long long rows = (long long)B * H;
-    const long long tiles = (long long)(Co / 16) * ((Ci + 63) / 64);
+    const int cib = wgrad_cib(Ci);
+    const long long tiles = (long long)(Co / 16) * ((Ci + cib - 1) / cib);
     long long chunks = (1024 + tiles - 1) / tiles;
     if (chunks > rows) chunks = rows;
     if (chunks < 1) chunks = 1;
@@ -623,8 +645,15 @@ hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part
     if (Ci % 16 || Co % 16 || B < 1 || H < 1 || W < 1) return hipErrorInvalidValue;
     const int chunks = conv3x3_wgrad_chunks(B, H, W, Ci, Co);
     const int per = (int)(((long long)B * H + chunks - 1) / chunks);
-    hipLaunchKernelGGL(conv3x3_wgrad_kernel, dim3(chunks, (Co / 16) * ((Ci + 63) / 64)), dim3(256), 0, s,
-                       static_cast<const bf16 *>(dpre), static_cast<const bf16 *>(in), part, B, H, W, Ci, Co, per);
+    const int cib = wgrad_cib(Ci);
+    const dim3 grid(chunks, (Co / 16) * ((Ci + cib - 1) / cib));
+    const bf16 *d = static_cast<const bf16 *>(dpre), *x = static_cast<const bf16 *>(in);
+    if (cib == 16)
+        hipLaunchKernelGGL(conv3x3_wgrad_kernel<16>, grid, dim3(256), 0, s, d, x, part, B, H, W, Ci, Co, per);
+    else if (cib == 32)
+        hipLaunchKernelGGL(conv3x3_wgrad_kernel<32>, grid, dim3(256), 0, s, d, x, part, B, H, W, Ci, Co, per);
+    else
+        hipLaunchKernelGGL(conv3x3_wgrad_kernel<64>, grid, dim3(256), 0, s, d, x, part, B, H, W, Ci, Co, per);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long n = (long long)Co * 9 * Ci;
