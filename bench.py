@@ -106,14 +106,23 @@ def cpu_baseline(w, steps: int):
                        contacts=w["contacts"], tau=w["tau"], F=w["F"])
     i = w["init"]
     O.init_fields(i["n"], i["T"], i["vx"], i["vy"])
+    lib = oracle.lib()
+    cores = lib.orc_get_threads()
     t0 = time.perf_counter()
     O.run(steps)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    cores = min(cores, os.cpu_count() or cores)
+    # the same oracle on one thread, over a twentieth of the steps
+    s1 = max(1, steps // 20)
+    lib.orc_set_threads(1)
+    t1 = time.perf_counter()
+    O.run(s1)
+    d1 = time.perf_counter() - t1
+    lib.orc_set_threads(cores)
     return {"value": w["nx"] * w["ny"] * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{w['nx']}x{w['ny']} graphene sample, {steps} steps from the uniform start, FP64, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "single_thread": {"value": w["nx"] * w["ny"] * s1 / d1 / 1e6, "unit": "MLUPS",
+                              "sample": f"the next {s1} steps, {d1:.1f} s"}}
 
 
 def copy_calibration(nbytes: int, reps: int = 20):

@@ -55,6 +55,10 @@ def lib() -> ctypes.CDLL:
     L.orc_stencil_new.restype = vp
     L.orc_stencil_new.argtypes = [_dp, _dp, _dp, _dp, _ip, _ip, _ip, _dp, _dp, _dp]
     L.orc_stencil_free.argtypes = [vp]
+    L.orc_set_threads.argtypes = [ctypes.c_int]
+    L.orc_set_threads.restype = None
+    L.orc_get_threads.argtypes = []
+    L.orc_get_threads.restype = ctypes.c_int
     L.orc_projections.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp]
     L.orc_moments.argtypes = [vp, _dp, _dp, _dp]
     L.orc_landau.argtypes = [_dp, _dp, _dp]

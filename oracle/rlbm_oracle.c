@@ -33,6 +33,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <float.h>
+#include <omp.h>
 
 #define Q 48
 #define K 16
@@ -82,6 +83,11 @@ orc_stencil *orc_stencil_new(const double *w, const double *p0, const double *px
 }
 
 void orc_stencil_free(orc_stencil *s) { free(s); }
+
+/* Worker threads of the lattice loops (timing of the CPU baseline only; the
+ * sums do not depend on it: each site is computed by one thread). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int orc_get_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------ Appendix B */
 
