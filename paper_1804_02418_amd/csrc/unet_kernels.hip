@@ -47,7 +47,11 @@ struct Mfma<16> {
 // ---------------------------------------------------------------- conv 3x3
 
 // grid.x = B * H * ceil(W / 64), grid.y = Co / 16; 4 wavefronts per block,
-// wavefront w covers pixels x0 + 16 w ... + 15 of one row.
+// wavefront w covers pixels x0 + 16 w ... + 15 of one row.  The block stages
+// the three input rows it needs (66 pixels: the segment and one on each
+// side, zero outside the image) and its 16 output channels' weights through
+// LDS, 64 input channels at a time, so that every input value is fetched
+// once per block instead of once per tap and wavefront.
 template <int KSTEP, bool RELU>
 __global__ __launch_bounds__(256) void conv3x3_fwd_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ w,
                                                           const float *__restrict__ bias, bf16 *__restrict__ out,
@@ -55,37 +59,57 @@ __global__ __launch_bounds__(256) void conv3x3_fwd_kernel(const bf16 *__restrict
 {
     typedef typename Mfma<KSTEP>::vec vec;
     constexpr int KPL = KSTEP / 4;  // channels per lane per K step
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int CC = 64, CP = CC + 8;  // channels per chunk, padded row (fewer bank conflicts)
+    __shared__ __attribute__((aligned(16))) bf16 Xs[3][66][CP];
+    __shared__ __attribute__((aligned(16))) bf16 Ws[16][9][CP];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int tiles_w = (W + 63) / 64;
-    int t = blockIdx.x;
-    const int xt = t % tiles_w;
-    t /= tiles_w;
-    const int y = t % H;
-    const int b = t / H;
-    const int x0 = xt * 64 + wave * 16;
-    if (x0 >= W) return;
+    int q = blockIdx.x;
+    const int xt = q % tiles_w;
+    q /= tiles_w;
+    const int y = q % H;
+    const int b = q / H;
+    const int xs = xt * 64, x0 = xs + wave * 16;
     const int co0 = blockIdx.y * 16;
     const int r = lane & 15;   // A row (pixel) and B column (channel)
     const int kq = lane >> 4;  // which group of KPL channels
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    vec zero;
-    for (int q = 0; q < KPL; ++q) zero[q] = (bf16)0.f;
-    for (int dy = 0; dy < 3; ++dy) {
-        const int yy = y + dy - 1;
-        const bool rowok = (unsigned)yy < (unsigned)H;
-        for (int dx = 0; dx < 3; ++dx) {
-            const int xx = x0 + r + dx - 1;
-            const bool ok = rowok && (unsigned)xx < (unsigned)W;
-            const long long pix = ok ? ((long long)b * H + yy) * W + xx : 0;
-            const bf16 *ip = in + pix * Ci + kq * KPL;
-            const bf16 *wp = w + ((long long)(co0 + r) * 9 + dy * 3 + dx) * Ci + kq * KPL;
-            for (int c0 = 0; c0 < Ci; c0 += KSTEP) {
-                const vec a = ok ? *reinterpret_cast<const vec *>(ip + c0) : zero;
-                const vec bv = *reinterpret_cast<const vec *>(wp + c0);
-                acc = Mfma<KSTEP>::run(a, bv, acc);
+    const bf16 z = (bf16)0.f;
+    for (int c0 = 0; c0 < Ci; c0 += CC) {
+        const int cc = Ci - c0 < CC ? Ci - c0 : CC;  // a multiple of 16
+        const int groups = cc / 8;
+        for (int unit = t; unit < 3 * 66 * groups; unit += 256) {
+            const int g = unit % groups, rest = unit / groups;
+            const int u = rest % 66, rr = rest / 66;
+            const int yy = y + rr - 1, xx = xs + u - 1;
+            bf16x8 v;
+            if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W)
+                v = *reinterpret_cast<const bf16x8 *>(in + (((long long)b * H + yy) * W + xx) * Ci + c0 + 8 * g);
+            else
+                for (int e = 0; e < 8; ++e) v[e] = z;
+            *reinterpret_cast<bf16x8 *>(&Xs[rr][u][8 * g]) = v;
+        }
+        for (int unit = t; unit < 16 * 9 * groups; unit += 256) {
+            const int g = unit % groups, rest = unit / groups;
+            const int tap = rest % 9, co = rest / 9;
+            *reinterpret_cast<bf16x8 *>(&Ws[co][tap][8 * g]) =
+                *reinterpret_cast<const bf16x8 *>(w + ((long long)(co0 + co) * 9 + tap) * Ci + c0 + 8 * g);
+        }
+        __syncthreads();
+        if (x0 < W) {
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3, dx = tap % 3;
+                for (int k0 = 0; k0 < cc; k0 += KSTEP) {
+                    const vec a = *reinterpret_cast<const vec *>(&Xs[dy][wave * 16 + r + dx][k0 + kq * KPL]);
+                    const vec bv = *reinterpret_cast<const vec *>(&Ws[r][tap][k0 + kq * KPL]);
+                    acc = Mfma<KSTEP>::run(a, bv, acc);
+                }
             }
         }
+        __syncthreads();
     }
+    if (x0 >= W) return;
     const int j = lane & 15;
     const float bj = bias ? bias[co0 + j] : 0.f;
 #pragma unroll
