@@ -243,9 +243,9 @@ def warm_vs_cold(path: str, count: int = 16, first_index: int = 6000, tol: float
 
 def batch_throughput(storage: str = "f32", count: int = 256, steps: int = 100, warmup: int = 10):
     """Aggregate throughput of the uneven-sample batch (`count` samples of the
-    batch generator, about 47 M sites at 256) advanced by the persistent
-    batched kernel: default launch shape without and with the step graph,
-    then after the batch autotuner.  HIP events on the batch's stream; the
+    batch generator, about 50 M sites at 256) advanced by the batched kernel,
+    one launch per step over every sample's blocks: default launch shape
+    without and with the step graph, then after the batch autotuner.  HIP events on the batch's stream; the
     timed call includes the per-call copy of the previous velocities and the
     field write of its last step."""
     import torch

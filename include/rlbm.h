@@ -282,11 +282,13 @@ void rlbm_batch_destroy(rlbm_batch *b);
  * (fields, residual, init for warm starts, checkpoints, ...) works on it. */
 rlbm_status rlbm_batch_lattice(rlbm_batch *b, int i, rlbm_lattice **lat);
 
-/* Advance every active sample by nsteps.  Each step is ONE launch of a
- * persistent kernel (as many blocks as fit on the device at once) whose
- * blocks walk the (sample, block) work items of all active samples in a
- * fixed interleaved order; with use_graph the launches are replayed from a
- * captured HIP graph.  Fields are kept for the last step.  RLBM_EINVAL if an
+/* Advance every active sample by nsteps.  Each step is ONE launch over the
+ * list of (sample, block) work items of all active samples, in sample
+ * order, one 256-thread block per item (each item is one block of that
+ * sample's own step grid: boundary band or row tile); the grid is the
+ * list's capacity and blocks past the current item count leave at once, so
+ * freezing samples needs no new graph.  With use_graph the launches are
+ * replayed from a captured HIP graph.  Fields are kept for the last step.  RLBM_EINVAL if an
  * active sample has the local-capacitance force on. */
 rlbm_status rlbm_batch_step(rlbm_batch *b, int64_t nsteps, int use_graph);
 

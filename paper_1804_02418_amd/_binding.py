@@ -322,8 +322,8 @@ class _BorrowedLattice(Lattice):
 
 
 class Batch:
-    """Many uneven lattices advanced together by the batched persistent
-    kernel (see rlbm_batch_* in include/rlbm.h)."""
+    """Many uneven lattices advanced together, one launch per step over all
+    samples' work items (see rlbm_batch_* in include/rlbm.h)."""
 
     def __init__(self, samples, storage="f32", stream=None):
         n = len(samples)

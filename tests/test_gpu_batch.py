@@ -1,4 +1,4 @@
-"""GPU tests of the batched persistent launch.
+"""GPU tests of the batched launch (all samples in one launch per step).
 
 Every sample of a batch must evolve bit-identically to the same lattice
 stepped alone (the step of a site is a pure function of the previous state,
