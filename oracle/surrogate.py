@@ -105,28 +105,48 @@ def relu(x):
     return np.maximum(x, 0.0)
 
 
+def bf16_round(a):
+    """Round to the nearest bfloat16 (IEEE binary32 with the significand cut
+    to 8 bits, ties to even), returned as float64.  The value is first
+    rounded to float32, the precision in which the kernels form what they
+    store, then the low 16 bits of the float32 pattern are dropped with
+    round-to-nearest-even (finite values only)."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64).reshape(np.shape(a))
+
+
 # ---------------------------------------------------------------- network
 
 class ReferenceUNet:
-    def __init__(self, base: int, cin: int, cout: int):
+    """store: None (every activation kept in float64) or a rounding applied
+    to each activation a network keeps in memory (the output of every
+    conv + bias + ReLU and of every pooling), so that a check of a network
+    that stores them at lower precision takes its ReLU decisions on the same
+    stored values; the backward pass is the same code either way."""
+
+    def __init__(self, base: int, cin: int, cout: int, store=None):
         self.base, self.cin, self.cout = base, cin, cout
+        self.store = store if store is not None else (lambda a: a)
 
     def forward(self, theta, x):
         P = unpack(theta, self.base, self.cin, self.cout)
         cache = {"x": x}
+        st = self.store
 
         def block(h, a, b_):
-            h1 = relu(conv(h, *P[a]))
-            h2 = relu(conv(h1, *P[b_]))
+            h1 = st(relu(conv(h, *P[a])))
+            h2 = st(relu(conv(h1, *P[b_])))
             cache[a] = (h, h1)
             cache[b_] = (h1, h2)
             return h2
 
         e1 = block(x, "e1a", "e1b")
-        e2 = block(pool(e1), "e2a", "e2b")
-        e3 = block(pool(e2), "e3a", "e3b")
-        e4 = block(pool(e3), "e4a", "e4b")
-        bt = block(pool(e4), "ba", "bb")
+        e2 = block(st(pool(e1)), "e2a", "e2b")
+        e3 = block(st(pool(e2)), "e3a", "e3b")
+        e4 = block(st(pool(e3)), "e4a", "e4b")
+        bt = block(st(pool(e4)), "ba", "bb")
         d4 = block(np.concatenate([up(bt), e4], axis=3), "d4a", "d4b")
         d3 = block(np.concatenate([up(d4), e3], axis=3), "d3a", "d3b")
         d2 = block(np.concatenate([up(d3), e2], axis=3), "d2a", "d2b")

@@ -10,7 +10,7 @@ state as it found it.
 import numpy as np
 import pytest
 
-from harness import gpu_lattice
+from harness import field_errors, gpu_lattice, oracle_lattice
 from paper_1804_02418_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -114,3 +114,41 @@ def test_batch_step_until_freezes_converged_samples():
     assert ((r < 1e-3) | (steps == 400)).all()
     for k, bl in enumerate(B.lattices):
         assert bl.time == steps[k]
+
+
+def test_full_batch_sampled_samples_against_oracle():
+    """The 256-sample uneven batch (about 50 M sites, FP32) as the bench runs
+    it (batch autotuner, graph replays of the step): after 40 steps, samples
+    of the extreme and awkward shapes (fewest and most sites, widths 128 and
+    192, height 128, widths that are not a multiple of 256) are each checked
+    for one step at every site against the oracle (FP64) applied to the
+    decoded GPU state, to the FP32 rounding of the stored deviations."""
+    import oracle
+    import paper_1804_02418_amd as rl
+
+    ws = workloads.batch_samples(256)
+    sites = [w["nx"] * w["ny"] for w in ws]
+    pick = {int(np.argmin(sites)), int(np.argmax(sites))}
+    for cond in (lambda w: w["nx"] == 128, lambda w: w["nx"] == 192, lambda w: w["ny"] == 128,
+                 lambda w: w["nx"] % 256 == 64 and w["nx"] > 256):
+        pick.add(next(k for k, w in enumerate(ws) if cond(w)))
+    B = rl.Batch(ws, "f32")
+    B.autotune(5)
+    B.step(40, graph=True)
+    fstar = {k: B.lattices[k].read_populations() for k in sorted(pick)}
+    B.step(1, graph=True)
+    wfull = np.array(oracle.stencil().w)[:, None, None]
+    for k in sorted(pick):
+        got = B.lattices[k].read_fields()
+        got_f = B.lattices[k].read_populations()
+        O = oracle_lattice(ws[k])
+        fpre = np.empty_like(fstar[k])
+        oracle.lib().orc_lattice_stream(O._h, oracle._ptr(np.ascontiguousarray(fstar[k])), oracle._ptr(fpre))
+        O.f = fpre
+        ref = O.fields()
+        exp_f = O.post_collision()
+        e = field_errors(got, ref)
+        perr = np.abs(got_f - exp_f).max() / np.abs(exp_f - wfull).max()
+        print("batch sample", k, (ws[k]["nx"], ws[k]["ny"]), e, "populations", perr, flush=True)
+        assert e["err_n"] <= 1e-9 and e["err_u"] <= 1e-5 and perr <= 1e-5, (k, e, perr)
+    B.close()

@@ -68,6 +68,48 @@ def test_bench_configuration_one_step_against_oracle():
     assert e["err_n"] <= 1e-9 and e["err_u"] <= 1e-5 and perr <= 1e-5
 
 
+@pytest.mark.parametrize("storage,tol_f", [("f64", 1e-12), ("f32", 1e-5), ("f16dev", 1e-3)])
+def test_large_sample_one_step_against_oracle(storage, tol_f):
+    """4096 x 2048 graphene sample (contacts 128 wide, 512 from the centre) in
+    the launch configuration the autotuner picks at that size (row tiles of
+    256 sites, streaming stores): after 200 GPU steps, the oracle (FP64)
+    streams and collides the decoded GPU state, and the GPU's next step must
+    agree at every site.  FP64 to the parity bound; FP32 and FP16 deviations
+    to the rounding of the stored deviation (2^-24 and 2^-11 of it: bounds
+    1e-5 and 1e-3 of the largest deviation), their fields (FP32 moment sums
+    of the same decoded values, FP64 Landau solve) as in the 1024 x 512
+    check."""
+    import oracle
+
+    w = workloads.graphene_sample(4096, 2048)
+    G = gpu_lattice(w, storage)
+    G.set_launch_shape(256, 1)
+    G.set_streaming_stores(True)
+    G.step(200)
+    fstar = G.read_populations()
+    G.step(1)
+    got = G.read_fields()
+    got_f = G.read_populations()
+    G.close()
+    O = oracle_lattice(w)
+    fpre = np.empty_like(fstar)
+    oracle.lib().orc_lattice_stream(O._h, oracle._ptr(np.ascontiguousarray(fstar)), oracle._ptr(fpre))
+    del fstar
+    O.f = fpre
+    ref = O.fields()
+    exp_f = O.post_collision()
+    e = field_errors(got, ref)
+    if storage == "f64":
+        perr = np.abs(got_f - exp_f).max() / np.abs(exp_f).max()
+        bound_n = bound_u = 1e-12
+    else:
+        wfull = np.array(oracle.stencil().w)[:, None, None]
+        perr = np.abs(got_f - exp_f).max() / np.abs(exp_f - wfull).max()
+        bound_n, bound_u = 1e-9, 1e-5
+    print(storage, "4096x2048 one step", e, "populations", perr, flush=True)
+    assert e["err_n"] <= bound_n and e["err_u"] <= bound_u and perr <= tol_f, (e, perr)
+
+
 def test_autotune_keeps_state_and_results():
     w = workloads.small_device(nx=300, ny=60, steps=5)
     a = gpu_lattice(w, "f32")

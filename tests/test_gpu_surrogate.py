@@ -59,8 +59,31 @@ def test_conv3x3_forward_matches_reference(ci, co, relu):
     assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("ci,co,relu,H,W", [(16, 16, True, 6, 256), (48, 32, False, 5, 200), (32, 16, True, 4, 130)])
+def test_conv3x3_forward_wide_images(ci, co, relu, H, W):
+    """Images wider than one 64-pixel tile of the forward kernel, also with a
+    ragged last tile: the halo between tiles comes from the neighbour's
+    pixels, zero only outside the image."""
+    import paper_1804_02418_amd as rl
+
+    torch = _torch()
+    rng = np.random.default_rng(ci + co + W)
+    x = _bf16_round(rng.normal(size=(1, H, W, ci)))
+    w = _bf16_round(rng.normal(size=(co, 3, 3, ci)) / np.sqrt(9 * ci))
+    b = rng.normal(size=co).astype(np.float32)
+    y = torch.empty((1, H, W, co), dtype=torch.bfloat16, device="cuda")
+    rl.conv3x3_forward(_dev_bf16(x), _dev_bf16(w), torch.from_numpy(b).cuda(), y, relu=relu)
+    torch.cuda.synchronize()
+    ref = S.conv(x, w, b.astype(np.float64))
+    if relu:
+        ref = np.maximum(ref, 0)
+    got = _host(y)
+    print("conv fwd wide", ci, co, W, "max err", np.abs(got - ref).max(), flush=True)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
+
+
 @pytest.mark.parametrize("ci,co,B,H,W", [(16, 32, 2, 16, 32), (48, 16, 2, 16, 32), (80, 32, 3, 20, 48),
-                                         (128, 16, 2, 160, 16)])
+                                         (128, 16, 2, 160, 16), (16, 16, 1, 6, 256), (32, 16, 2, 3, 200)])
 def test_conv3x3_backward_kernels_match_reference(ci, co, B, H, W):
     """Also partial 64-channel blocks, widths that are not a multiple of the
     32-pixel segment, and several row chunks (320 rows of 16 pixels)."""
@@ -127,6 +150,102 @@ def test_network_forward_and_backward_match_reference():
     assert fwd_err < 3e-2
     assert abs(loss - lr_) < 2e-2 * lr_
     assert cos > 0.999 and rel < 5e-2
+
+
+def _kernel_params(theta, base, cin, cout):
+    """Parameters as the kernels use them: weights in bfloat16, biases in FP32."""
+    out = theta.astype(np.float64).copy()
+    off = 0
+    for _, ci, co, k in S.layer_list(base, cin, cout):
+        n = co * k * k * ci
+        out[off:off + n] = _bf16_round(out[off:off + n])
+        off += n + co
+    return out
+
+
+def _bench_size_run(theta, x, dy):
+    """Forward of the batch x, then the backward of dy; returns the output,
+    the parameter gradient and the input gradient (host, float64)."""
+    import paper_1804_02418_amd as rl
+
+    torch = _torch()
+    B, H, W, cin = x.shape
+    cout = dy.shape[-1]
+    net = rl.UNet(16, cin, cout, H, W, max_batch=B)
+    net.set_params(theta)
+    y = torch.empty((B, H, W, cout), dtype=torch.float32, device="cuda")
+    net.forward(torch.from_numpy(x.astype(np.float32)).cuda(), y)
+    dx = torch.empty((B, H, W, cin), dtype=torch.float32, device="cuda")
+    net.zero_grad()
+    net.backward(torch.from_numpy(dy.astype(np.float32)).cuda(), dx)
+    g = net.get_grads().astype(np.float64)
+    out = y.cpu().numpy().astype(np.float64), g, dx.cpu().numpy().astype(np.float64)
+    net.close()
+    return out
+
+
+def test_network_at_bench_size_matches_reference():
+    """The production network (base 16, 16 input and 3 output channels) at
+    the bench's launch configuration, a batch of 8 images of 256 x 256,
+    against the reference, which keeps its activations in bfloat16 as the
+    network does (FP64 arithmetic otherwise) so that both sides take their
+    ReLU decisions on the same stored values.
+
+    Outputs: two images of a He-initialised network.  Gradients: that
+    network's are chaotic under rounding (one-ulp changes to 0.1% of the
+    inputs move the reference's own gradient by 7-9%, because pre-activations
+    within rounding of zero switch sides and gradients sum terms of random
+    sign), so they are checked on a network that takes no decision near
+    zero: weights scaled by 1/8 and biases of +1 keep every activation of
+    the reference above 0.05 (its gradient moves by under 0.1% under the same
+    perturbation).  The output gradient is non-zero on one image only; the
+    other seven must add nothing."""
+    base, cin, cout, B, H, W = 16, 16, 3, 8, 256, 256
+    rng = np.random.default_rng(11)
+    x = _bf16_round(rng.normal(size=(B, H, W, cin)))
+    dy = np.zeros((B, H, W, cout))
+    # with a mean (as the loss gradient of a biased prediction has), so that
+    # the sums over pixels that every bias and, in a network whose
+    # activations sit near 1, every weight gradient contain do not cancel
+    # (a zero-mean draw can leave them several times below the size of their
+    # terms, and their rounding error then looks large beside them)
+    dy[3] = rng.normal(size=(H, W, cout)) + 0.5
+    ref = S.ReferenceUNet(base, cin, cout, store=S.bf16_round)
+
+    theta = S.he_init(base, cin, cout, 11).astype(np.float32)
+    theta[-cout:] = rng.normal(size=cout)
+    got, _, _ = _bench_size_run(theta, x, dy)
+    for k in (0, 3):
+        yr, _ = ref.forward(_kernel_params(theta, base, cin, cout), x[k:k + 1])
+        fwd_err = np.abs(got[k] - yr[0]).max() / np.abs(yr).max()
+        print("image", k, "fwd rel err", fwd_err, flush=True)
+        assert fwd_err < 3e-2
+
+    theta = S.he_init(base, cin, cout, 12).astype(np.float32)
+    off = 0
+    for _, ci, co, k in S.layer_list(base, cin, cout):
+        n = co * k * k * ci
+        theta[off:off + n] *= 0.125
+        theta[off + n:off + n + co] = 1.0
+        off += n + co
+    got, g, gdx = _bench_size_run(theta, x, dy)
+    tb = _kernel_params(theta, base, cin, cout)
+    yr, cache = ref.forward(tb, x[3:4])
+    names = [l[0] for l in S.layer_list(base, cin, cout)]
+    amin = min(float(cache[n][1].min()) for n in names[:-1])
+    assert amin > 0.05, amin
+    assert np.abs(got[3] - yr[0]).max() <= 1e-2 * np.abs(yr).max()
+    gr, dxr = ref.backward(tb, cache, dy[3:4])
+    Pg, Pr = S.unpack(g, base, cin, cout), S.unpack(gr, base, cin, cout)
+    errs = {n: tuple(round(float(np.linalg.norm(Pg[n][j] - Pr[n][j]) / np.linalg.norm(Pr[n][j])), 5) for j in (0, 1))
+            for n in names}
+    edx = float(np.linalg.norm(gdx[3] - dxr[0]) / np.linalg.norm(dxr))
+    print("256x256 conditioned: min activation", amin, "input gradient", edx, "per layer (weights, biases)", errs,
+          flush=True)
+    for n, e in errs.items():
+        assert max(e) <= 2e-2, (n, e)
+    assert edx <= 2e-2
+    assert not np.any(np.delete(gdx, 3, axis=0))
 
 
 def test_adam_training_reduces_loss():

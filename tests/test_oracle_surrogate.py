@@ -74,3 +74,41 @@ def test_network_gradient_matches_finite_differences(seed):
         e[i] = h
         fd = (loss(theta, x + e) - loss(theta, x - e)) / (2 * h)
         assert abs(fd - gx[i]) <= 1e-6 * max(1e-3, abs(gx[i])) + 1e-9, (i, fd, gx[i])
+
+
+def test_bf16_round_matches_torch_conversion():
+    """The reference's bfloat16 rounding against torch's CPU conversion (a
+    library routine with round-to-nearest-even): random values over many
+    magnitudes, both signs, zero, and exact ties with even and odd kept
+    bits."""
+    import torch
+
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=4000) * 10.0 ** rng.integers(-30, 30, size=4000)
+    ties = np.array([0x3F808000, 0x3F818000, 0xBF808000, 0xBF818000, 0x4049_8000, 0x0080_8000],
+                    dtype=np.uint32).view(np.float32).astype(np.float64)
+    a = np.concatenate([a, ties, [0.0, -0.0, 1.0, -2.5]])
+    ref = torch.from_numpy(a.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    got = S.bf16_round(a)
+    assert np.array_equal(got, ref)
+    # ties go to the even pattern
+    assert S.bf16_round(ties[:2]).tolist() == [1.0, 1.015625]
+
+
+def test_stored_rounding_only_rounds_what_is_stored():
+    """With the identity as the store rounding the network is the plain FP64
+    one bit for bit; with bfloat16 every kept activation is a bfloat16 value
+    and the output stays within bfloat16 rounding of the FP64 output."""
+    base, cin, cout = 4, 3, 2
+    rng = np.random.default_rng(2)
+    theta = S.he_init(base, cin, cout, 2)
+    x = S.bf16_round(rng.normal(size=(2, 32, 32, cin)))
+    y0, _ = S.ReferenceUNet(base, cin, cout).forward(theta, x)
+    y1, _ = S.ReferenceUNet(base, cin, cout, store=lambda v: v).forward(theta, x)
+    assert np.array_equal(y0, y1)
+    yb, cache = S.ReferenceUNet(base, cin, cout, store=S.bf16_round).forward(theta, x)
+    for name, _, _, _ in S.layer_list(base, cin, cout)[:-1]:
+        out = cache[name][1]
+        assert np.array_equal(S.bf16_round(out), out), name
+    assert np.abs(yb - y0).max() <= 2e-2 * np.abs(y0).max()
+    assert not np.array_equal(yb, y0)
