@@ -245,9 +245,9 @@ def batch_throughput(storage: str = "f32", count: int = 256, steps: int = 100, w
     """Aggregate throughput of the uneven-sample batch (`count` samples of the
     batch generator, about 50 M sites at 256) advanced by the batched kernel,
     one launch per step over every sample's blocks: default launch shape
-    without and with the step graph, then after the batch autotuner.  HIP events on the batch's stream; the
-    timed call includes the per-call copy of the previous velocities and the
-    field write of its last step."""
+    without and with the step graph, then after the batch autotuner.  HIP
+    events on the batch's stream; the timed call includes the per-call copy
+    of the previous velocities and the field write of its last step."""
     import torch
 
     import paper_1804_02418_amd as rl
@@ -346,6 +346,8 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-sample batched-kernel throughput")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate network throughput")
     ap.add_argument("--surrogate-only", action="store_true", help="only time the surrogate network")
+    ap.add_argument("--batch-only", action="store_true", help="only time the 256-sample batch")
+    ap.add_argument("--batch-steps", type=int, default=100, help="timed steps per batch configuration")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the other storages at this size and the three storages at 4096x2048")
     ap.add_argument("--copy-bytes", type=int, default=0, help="only run the copy-bandwidth calibration")
@@ -357,6 +359,9 @@ def main(argv=None):
         return 0
     if args.surrogate_only:
         print(json.dumps({"surrogate": surrogate_throughput()}), flush=True)
+        return 0
+    if args.batch_only:
+        print(json.dumps({"batch_256": batch_throughput(steps=args.batch_steps)}), flush=True)
         return 0
 
     if args.gpus != 1:
