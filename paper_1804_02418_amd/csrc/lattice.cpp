@@ -54,7 +54,9 @@ rlbm_status fail(rlbm_status st, const char *fmt, ...)
 #define HIP_TRY(expr)                                                                              \
     do {                                                                                           \
         hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) return fail(RLBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? RLBM_ENOMEM : RLBM_EDEVICE, "%s: %s", #expr,   \
+                        hipGetErrorString(e_));                                                    \
     } while (0)
 
 struct Consts {
@@ -499,12 +501,12 @@ rlbm_status rlbm_set_boundaries(rlbm_lattice *L, int periodic_x, int periodic_y,
         if (k.edge < 0 || k.edge > 3) return fail(RLBM_EINVAL, "contact %d: bad edge %d", c, k.edge);
         const bool horiz = k.edge == RLBM_EDGE_BOTTOM || k.edge == RLBM_EDGE_TOP;
         const int len = horiz ? L->nx : L->ny;
-        if (k.width < 1 || k.start < 0 || k.start + k.width > len)
+        if (k.width < 1 || k.start < 0 || (long long)k.start + k.width > len)
             return fail(RLBM_EINVAL, "contact %d: span [%d, %d) outside the edge (length %d)", c, k.start,
                         k.start + k.width, len);
         if ((horiz && periodic_y) || (!horiz && periodic_x))
             return fail(RLBM_EINVAL, "contact %d lies on a periodic edge", c);
-        if (!(k.n > 0) || !(k.T > 0) || !(k.vx * k.vx + k.vy * k.vy < 1.0))
+        if (!(k.n > 0) || !(k.T > 0) || !(k.vx * k.vx + k.vy * k.vy < 1.0) || !std::isfinite(k.n + k.T))
             return fail(RLBM_EINVAL, "contact %d: invalid state", c);
         for (int o = 0; o < c; ++o) {
             const rlbm_contact &m = contacts[o];
@@ -634,7 +636,8 @@ static rlbm_status do_init(rlbm_lattice *L, const double *n, const double *T, co
 rlbm_status rlbm_init_uniform(rlbm_lattice *L, double n, double T, double vx, double vy)
 {
     CHECK_L(L);
-    if (!(n > 0) || !(T > 0) || !(vx * vx + vy * vy < 1.0)) return fail(RLBM_EINVAL, "rlbm_init_uniform: invalid state");
+    if (!(n > 0) || !(T > 0) || !(vx * vx + vy * vy < 1.0) || !std::isfinite(n + T))
+        return fail(RLBM_EINVAL, "rlbm_init_uniform: invalid state");
     const double u[4] = {n, T, vx, vy};
     return do_init(L, nullptr, nullptr, nullptr, nullptr, u);
 }
@@ -671,7 +674,16 @@ rlbm_status rlbm_step(rlbm_lattice *L, int64_t nsteps)
     for (int64_t k = 0; k < nsteps; ++k) {
         set_write_fields(L, k == nsteps - 1);
         if (lca) set_lca_buffers(L, L->nlca[L->ncur], L->nlca[L->ncur ^ 1]);
-        HIP_TRY(launch_step(L->store(), L->args(), L->pop[L->cur], L->pop[1 - L->cur], L->shape, L->stream));
+        const hipError_t e = launch_step(L->store(), L->args(), L->pop[L->cur], L->pop[1 - L->cur], L->shape, L->stream);
+        if (e != hipSuccess) {
+            // the k steps launched before stand; the fields are not those of the state
+            set_write_fields(L, 0);
+            L->t += k;
+            L->last_K = k;
+            L->fields_valid = false;
+            return fail(RLBM_EDEVICE, "rlbm_step: step %lld of %lld: %s", (long long)k, (long long)nsteps,
+                        hipGetErrorString(e));
+        }
         L->cur ^= 1;
         if (lca) L->ncur ^= 1;
     }
@@ -839,6 +851,9 @@ rlbm_status rlbm_set_state(rlbm_lattice *L, const void *src, size_t bytes)
     if (h.lca != (L->inv_cg != 0.0 ? 1 : 0))
         return fail(RLBM_EINVAL, "rlbm_set_state: the state was saved with the local-capacitance force %s",
                     h.lca ? "on" : "off");
+    if (!(h.n_ref > 0) || !(h.T_ref > 0) || !(h.scale > 0) || !std::isfinite(h.n_ref + h.T_ref + h.scale) || h.t < 0 ||
+        h.last_K < 0)
+        return fail(RLBM_EINVAL, "rlbm_set_state: corrupt header");
     if (h.n_ref != L->n_ref || h.T_ref != L->T_ref || h.scale != L->scale) {
         L->n_ref = h.n_ref;
         L->T_ref = h.T_ref;
@@ -1113,7 +1128,14 @@ rlbm_status ensure_graph(rlbm_batch *B)
     }
     if (e != hipSuccess) return fail(RLBM_EDEVICE, "graph capture: %s", hipGetErrorString(e));
     B->graph = g;
-    HIP_TRY(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        // keep no half-built graph: the next call captures afresh
+        (void)hipGraphDestroy(B->graph);
+        B->graph = nullptr;
+        B->exec = nullptr;
+        return fail(RLBM_EDEVICE, "graph instantiation: %s", hipGetErrorString(e));
+    }
     return RLBM_OK;
 }
 
