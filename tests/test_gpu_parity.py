@@ -170,6 +170,39 @@ def test_invalid_tau_and_unstable_state():
         G.residual()
 
 
+def test_invalid_states_and_corrupt_checkpoints_are_rejected():
+    """Non-finite initial states and contact states, contact spans whose end
+    overflows, and a checkpoint header with a corrupt reference state give
+    RLBM_EINVAL and leave the lattice as it was."""
+    import struct
+
+    import paper_1804_02418_amd as rl
+
+    w = workloads.small_device(nx=64, ny=16, steps=4)
+    G = gpu_lattice(w, "f64")
+    G.step(2)
+    before = G.read_populations()
+    for args in ((float("inf"), 1.0, 0.0, 0.0), (1.0, float("inf"), 0.0, 0.0)):
+        with pytest.raises(rl.RlbmError) as ei:
+            G.init_uniform(*args)
+        assert ei.value.status == -1
+    bad = [dict(edge="bottom", start=2**31 - 10, width=100, n=1.0, T=1.0, vx=0.0, vy=0.0),
+           dict(edge="bottom", start=4, width=8, n=float("inf"), T=1.0, vx=0.0, vy=0.0)]
+    for c in bad:
+        with pytest.raises(rl.RlbmError) as ei:
+            G.set_boundaries(False, False, [c])
+        assert ei.value.status == -1
+    blob = bytearray(G.get_state())
+    # header: magic u64, version/nx/ny/storage i32, t/last_K i64, n_ref/T_ref/scale f64
+    off_scale = 8 + 4 * 4 + 2 * 8 + 2 * 8
+    blob[off_scale:off_scale + 8] = struct.pack("<d", 0.0)
+    with pytest.raises(rl.RlbmError) as ei:
+        G.set_state(bytes(blob))
+    assert ei.value.status == -1
+    assert G.time == 2
+    assert np.array_equal(G.read_populations(), before)
+
+
 @pytest.mark.parametrize("shape", [(64, 4), (128, 2), (256, 1)])
 @pytest.mark.parametrize("xcd", [False, True])
 def test_launch_shapes_agree(shape, xcd):
