@@ -147,6 +147,27 @@ def copy_calibration(nbytes: int, reps: int = 20):
             "ms_per_copy": round(ms, 4)}
 
 
+def bandwidth_probes():
+    """Practical bandwidth ceilings for the step: read, copy and the 48-plane
+    pull pattern (trivial arithmetic) on arrays the size of one population
+    array, plus torch's device copy, HIP events (include/rlbm_probe.h)."""
+    from paper_1804_02418_amd import _binding as B
+
+    rows = []
+    for nx, ny, reps in ((4096, 2048, 20), (1024, 512, 200)):
+        for pattern, nt in (("read", False), ("copy", False), ("copy", True)):
+            g, u = B.bandwidth_probe(pattern, 4, nx, ny, nt, reps)
+            rows.append({"pattern": pattern, "nontemporal": nt, "array_bytes": 48 * 4 * nx * ny, "GBs": round(g, 1),
+                         "us": round(u, 2)})
+    for elem, nx, ny, reps in ((4, 4096, 2048, 20), (2, 4096, 2048, 20), (8, 4096, 2048, 10), (4, 1024, 512, 200)):
+        for nt in (False, True):
+            g, u = B.bandwidth_probe("pull48", elem, nx, ny, nt, reps)
+            rows.append({"pattern": "pull48", "elem_bytes": elem, "nx": nx, "ny": ny, "nontemporal": nt,
+                         "GBs": round(g, 1), "us": round(u, 2)})
+    rows.append(dict(pattern="torch device copy", **copy_calibration(1 << 30)))
+    return rows
+
+
 WEIGHTS = os.path.join(HERE, "paper_1804_02418_amd", "data", "unet_graphene256.npz")
 
 
@@ -347,6 +368,8 @@ def main(argv=None):
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate network throughput")
     ap.add_argument("--surrogate-only", action="store_true", help="only time the surrogate network")
     ap.add_argument("--batch-only", action="store_true", help="only time the 256-sample batch")
+    ap.add_argument("--bandwidth-probes", action="store_true",
+                    help="only measure read, copy and 48-plane pull bandwidth (the practical ceilings)")
     ap.add_argument("--batch-steps", type=int, default=100, help="timed steps per batch configuration")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the other storages at this size and the three storages at 4096x2048")
@@ -359,6 +382,10 @@ def main(argv=None):
         return 0
     if args.surrogate_only:
         print(json.dumps({"surrogate": surrogate_throughput()}), flush=True)
+        return 0
+    if args.bandwidth_probes:
+        for row in bandwidth_probes():
+            print(json.dumps(row), flush=True)
         return 0
     if args.batch_only:
         print(json.dumps({"batch_256": batch_throughput(steps=args.batch_steps)}), flush=True)

@@ -70,6 +70,8 @@ SIGNATURES = {
                                 None),
     "rlbm_quadrature_massless": ([ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_uint64,
                                   ctypes.c_int, _dp, _dp, _dp, _dp], None),
+    "rlbm_bandwidth_probe": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp,
+                              _dp, _dp], None),
     "rlbm_set_block_order": ([_vp, ctypes.c_int], None),
     "rlbm_batch_set_block_order": ([_vp, ctypes.c_int], None),
     "rlbm_set_reference": ([_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double], None),
@@ -402,6 +404,19 @@ class Batch:
 
 class NotFound(RlbmError):
     pass
+
+
+PROBE_PATTERNS = {"read": 0, "copy": 1, "pull48": 2}
+
+
+def bandwidth_probe(pattern: str, elem_bytes: int, nx: int, ny: int, nontemporal: bool = False, reps: int = 10,
+                    stream=None):
+    """(GB/s, us per launch) of a read, copy or 48-plane pull over arrays the
+    size of one population array of an nx x ny lattice (include/rlbm_probe.h)."""
+    g, u = ctypes.c_double(), ctypes.c_double()
+    check(lib().rlbm_bandwidth_probe(PROBE_PATTERNS[pattern], int(elem_bytes), int(nx), int(ny), int(bool(nontemporal)),
+                                     int(reps), _vp(stream) if stream else None, ctypes.byref(g), ctypes.byref(u)))
+    return g.value, u.value
 
 
 def mj_moment(mbar: float, a: int, b: int, c: int) -> float:

@@ -1,0 +1,185 @@
+// Bandwidth probes (measurement helper; see include/rlbm_probe.h): read,
+// copy and the step's 48-plane pull pattern with trivial arithmetic, timed
+// with HIP events.  Every index is bounded: the read and copy kernels test
+// each element index against the element count, and the pull kernel
+// touches only sites with x, y in [5, n - 5), whose sources lie inside the
+// 48-plane array.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <string>
+
+#include "../../include/rlbm_probe.h"
+#include "rlbm_math.h"
+
+namespace rlbm {
+rlbm_status set_error(rlbm_status st, const char *msg);
+}
+
+using namespace rlbm;
+
+namespace {
+
+// Read and copy: each block moves 1024 consecutive 16-byte elements, each
+// thread four of them 256 apart (coalesced), all loads issued before any
+// store so that four requests per thread are in flight.
+constexpr int kPerThread = 4;
+
+__global__ __launch_bounds__(256) void probe_read(const float4 *__restrict__ a, float *__restrict__ sink, size_t n)
+{
+    const size_t base = (size_t)blockIdx.x * (256 * kPerThread) + threadIdx.x;
+    float4 v[kPerThread];
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) {
+        const size_t i = base + (size_t)u * 256;
+        v[u] = i < n ? a[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) s += v[u].x + v[u].y + v[u].z + v[u].w;
+    // a store the compiler cannot drop, which (the array being zero) never happens
+    if (s == -1.0f) sink[0] = s;
+}
+
+template <bool NT>
+__global__ __launch_bounds__(256) void probe_copy(const float4 *__restrict__ a, float4 *__restrict__ b, size_t n)
+{
+    const size_t base = (size_t)blockIdx.x * (256 * kPerThread) + threadIdx.x;
+    float4 v[kPerThread];
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) {
+        const size_t i = base + (size_t)u * 256;
+        if (i < n) v[u] = a[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) {
+        const size_t i = base + (size_t)u * 256;
+        if (i >= n) continue;
+        if constexpr (NT) {
+            __builtin_nontemporal_store(v[u].x, &b[i].x);
+            __builtin_nontemporal_store(v[u].y, &b[i].y);
+            __builtin_nontemporal_store(v[u].z, &b[i].z);
+            __builtin_nontemporal_store(v[u].w, &b[i].w);
+        } else {
+            b[i] = v[u];
+        }
+    }
+}
+
+// One interior site per thread: the 48 hop-shifted loads of a pull, their
+// sum as the only arithmetic, and 48 aligned stores.
+template <class T, bool NT>
+__global__ __launch_bounds__(256) void probe_pull48(const T *__restrict__ src, T *__restrict__ dst, int nx, int ny,
+                                                   long long P)
+{
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int y = kReach + blockIdx.y;
+    if (x < kReach || x >= nx - kReach || y >= ny - kReach) return;
+    const long long site = (long long)y * nx + x;
+    float h[kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int d = i / kShells;
+        h[i] = (float)src[(long long)i * P + site - ((long long)kCy[d] * nx + kCx[d])];
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) s += h[i];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const T v = (T)(0.5f * h[i] + 1e-9f * s);
+        if constexpr (NT)
+            __builtin_nontemporal_store(v, &dst[(long long)i * P + site]);
+        else
+            dst[(long long)i * P + site] = v;
+    }
+}
+
+template <class T>
+hipError_t launch_pull(const void *a, void *b, int nx, int ny, int nt, hipStream_t s)
+{
+    const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)(ny - 2 * kReach));
+    const long long P = (long long)nx * ny;
+    if (nt)
+        hipLaunchKernelGGL((probe_pull48<T, true>), grid, dim3(256), 0, s, static_cast<const T *>(a),
+                           static_cast<T *>(b), nx, ny, P);
+    else
+        hipLaunchKernelGGL((probe_pull48<T, false>), grid, dim3(256), 0, s, static_cast<const T *>(a),
+                           static_cast<T *>(b), nx, ny, P);
+    return hipGetLastError();
+}
+
+rlbm_status probe_fail(rlbm_status st, const char *what, hipError_t e)
+{
+    const std::string m = std::string("rlbm_bandwidth_probe: ") + what + ": " + hipGetErrorString(e);
+    return set_error(e == hipErrorOutOfMemory ? RLBM_ENOMEM : st, m.c_str());
+}
+
+}  // namespace
+
+extern "C" rlbm_status rlbm_bandwidth_probe(int pattern, int elem_bytes, int nx, int ny, int nontemporal, int reps,
+                                            void *hip_stream, double *gbs, double *us)
+{
+    if (pattern < RLBM_PROBE_READ || pattern > RLBM_PROBE_PULL48 || (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) ||
+        nx <= 2 * kReach || ny <= 2 * kReach || ny - 2 * kReach > 65535 || reps < 1)
+        return set_error(RLBM_EINVAL, "rlbm_bandwidth_probe: invalid pattern, element size, size or repetitions");
+    const size_t bytes = (size_t)kQ * (size_t)nx * (size_t)ny * (size_t)elem_bytes;
+    if (bytes > (1ull << 34)) return set_error(RLBM_EINVAL, "rlbm_bandwidth_probe: array beyond 2^34 bytes");
+    // 48 x elem_bytes is a multiple of 16, so the array is whole float4s
+    const size_t n4 = bytes / 16;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    void *a = nullptr, *b = nullptr;
+    float *sink = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&a, bytes);
+    if (e == hipSuccess && pattern != RLBM_PROBE_READ) e = hipMalloc(&b, bytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&sink, sizeof(float));
+    if (e == hipSuccess) e = hipMemsetAsync(a, 0, bytes, s);
+    if (e == hipSuccess && b) e = hipMemsetAsync(b, 0, bytes, s);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const unsigned grid = (unsigned)((n4 + 256 * kPerThread - 1) / (256 * kPerThread));
+    auto one = [&](int k) -> hipError_t {
+        if (pattern == RLBM_PROBE_READ) {
+            hipLaunchKernelGGL(probe_read, dim3(grid), dim3(256), 0, s, static_cast<const float4 *>(a), sink, n4);
+            return hipGetLastError();
+        }
+        if (pattern == RLBM_PROBE_COPY) {
+            if (nontemporal)
+                hipLaunchKernelGGL((probe_copy<true>), dim3(grid), dim3(256), 0, s, static_cast<const float4 *>(a),
+                                   static_cast<float4 *>(b), n4);
+            else
+                hipLaunchKernelGGL((probe_copy<false>), dim3(grid), dim3(256), 0, s, static_cast<const float4 *>(a),
+                                   static_cast<float4 *>(b), n4);
+            return hipGetLastError();
+        }
+        const void *from = (k & 1) ? b : a;
+        void *to = (k & 1) ? a : b;
+        return elem_bytes == 2 ? launch_pull<_Float16>(from, to, nx, ny, nontemporal, s)
+               : elem_bytes == 4 ? launch_pull<float>(from, to, nx, ny, nontemporal, s)
+                                 : launch_pull<double>(from, to, nx, ny, nontemporal, s);
+    };
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = one(k);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) e = one(k + 1);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    const hipError_t ee = e;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    (void)hipFree(sink);
+    if (ee != hipSuccess) return probe_fail(RLBM_EDEVICE, "device", ee);
+    const double t = (double)ms / reps * 1e-3;
+    const double interior = (double)(nx - 2 * kReach) * (double)(ny - 2 * kReach);
+    const double moved = pattern == RLBM_PROBE_READ   ? (double)bytes
+                         : pattern == RLBM_PROBE_COPY ? 2.0 * (double)bytes
+                                                      : 2.0 * kQ * elem_bytes * interior;
+    if (gbs) *gbs = moved / t / 1e9;
+    if (us) *us = t * 1e6;
+    return RLBM_OK;
+}

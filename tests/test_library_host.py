@@ -114,3 +114,15 @@ def test_store_form_and_block_order_reject_bad_arguments():
 
     assert rl.lib().rlbm_set_streaming_stores(None, 1) == _binding.EINVAL
     assert rl.lib().rlbm_set_block_order(None, 0) == _binding.EINVAL
+
+
+def test_bandwidth_probe_rejects_bad_arguments():
+    """Checked before any device call: unknown pattern, element size, sizes
+    too small for the pull's interior, too many rows, no repetitions."""
+    import paper_1804_02418_amd as rl
+    from paper_1804_02418_amd import _binding as B
+
+    for args in ((5, 4, 64, 64, 0, 1), (0, 3, 64, 64, 0, 1), (2, 4, 10, 64, 0, 1), (2, 4, 64, 10, 0, 1),
+                 (2, 4, 64, 70000, 0, 1), (1, 4, 64, 64, 0, 0)):
+        st = rl.lib().rlbm_bandwidth_probe(*args, None, None, None)
+        assert st == B.EINVAL, (args, st)
