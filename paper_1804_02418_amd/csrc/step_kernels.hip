@@ -149,28 +149,36 @@ __device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, R
     const R U0 = R(u0 * A.tau_inv), Ux = R(ux * A.tau_inv), Uy = R(uy * A.tau_inv);
     // ---- equilibrium and force coefficients (deviation from the reference, / scale) ----
     R ad[kK];
-    appendix_b_each_sc(sc, T, u0, ux, uy, [&](int k, double v) { ad[k] = R((v - A.a_ref[k]) * A.inv_scale); });
+    // the reference rest state projects only onto kRestK (checked on the host
+    // at set-up), so the other coefficients need no subtraction
+    appendix_b_each_sc(sc, T, u0, ux, uy, [&](int k, double v) {
+        const bool rest = k == kRestK[0] || k == kRestK[1] || k == kRestK[2] || k == kRestK[3];
+        ad[k] = R((rest ? v - A.a_ref[k] : v) * A.inv_scale);
+    });
     R Hb[kK];
     if (has_force) {
         // b = (Fx C_x + Fy C_y) a / scale with a / scale = ad + a_ref / scale,
-        // accumulated in one array (the force components folded in)
-        R b[kK];
-#pragma unroll
-        for (int k = 0; k < kK; ++k) b[k] = R(0);
+        // row by row: the row's terms of C_x and of C_y with their constant
+        // coefficients, then the two force components once per row
         R arest[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) arest[r] = ad[kRestK[r]] + A.aref_s[r];
-#pragma unroll
-        for (int q = 0; q < kForceNx; ++q) {
-            const int m = kForceX[q].m;
+        auto coef = [&](int m) -> R {
             const int r = m == kRestK[0] ? 0 : m == kRestK[1] ? 1 : m == kRestK[2] ? 2 : m == kRestK[3] ? 3 : -1;
-            b[kForceX[q].k] += (fx * R(kForceX[q].v)) * (r >= 0 ? arest[r] : ad[m]);
-        }
+            return r >= 0 ? arest[r] : ad[m];
+        };
+        R b[kK];
 #pragma unroll
-        for (int q = 0; q < kForceNy; ++q) {
-            const int m = kForceY[q].m;
-            const int r = m == kRestK[0] ? 0 : m == kRestK[1] ? 1 : m == kRestK[2] ? 2 : m == kRestK[3] ? 3 : -1;
-            b[kForceY[q].k] += (fy * R(kForceY[q].v)) * (r >= 0 ? arest[r] : ad[m]);
+        for (int k = 0; k < kK; ++k) {
+            // -0 is the additive identity, so the first term is a plain product
+            R tx = R(-0.0), ty = R(-0.0);
+#pragma unroll
+            for (int q = 0; q < kForceNx; ++q)
+                if (kForceX[q].k == k) tx += R(kForceX[q].v) * coef(kForceX[q].m);
+#pragma unroll
+            for (int q = 0; q < kForceNy; ++q)
+                if (kForceY[q].k == k) ty += R(kForceY[q].v) * coef(kForceY[q].m);
+            b[k] = fx * tx + fy * ty;
         }
         appendix_a_to_harmonics(b, Hb);
     } else {
