@@ -495,11 +495,11 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
     collide_site<R>(h, A, fx, fy, MODE != kNoForce, store, fields);
 }
 
-// At most four waves per SIMD: measured on MI355X, the compiler's schedule
-// for that budget (about 110 VGPRs) beats the five-wave one (96 VGPRs) on
-// FP32 at 4096 x 2048 by 2% and is level elsewhere.
+// At most four waves per SIMD for FP32 and FP64 storage, five for FP16:
+// measured on MI355X, five waves (93-95 VGPRs, no spills) make FP16 3-4%
+// faster and FP32 1.3% slower than four.
 template <class S, class R, int MODE, int GATHER, bool NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void step_kernel(const StepArgs<R> A, const S *__restrict__ src,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, sizeof(S) == 2 ? 5 : 4))) void step_kernel(const StepArgs<R> A, const S *__restrict__ src,
                                                    S *__restrict__ dst, int nbnd, int tile_x, int tiles_x, int all,
                                                    int xcd)
 {
