@@ -152,3 +152,34 @@ def test_full_batch_sampled_samples_against_oracle():
         print("batch sample", k, (ws[k]["nx"], ws[k]["ny"]), e, "populations", perr, flush=True)
         assert e["err_n"] <= 1e-9 and e["err_u"] <= 1e-5 and perr <= 1e-5, (k, e, perr)
     B.close()
+
+
+def test_degenerate_batches_and_zero_steps():
+    """Zero steps change nothing (single lattice and batch); a batch whose
+    samples are all frozen launches nothing and changes nothing; a batch of
+    one sample is the single lattice bit for bit."""
+    import paper_1804_02418_amd as rl
+
+    ws = _samples()
+    L = gpu_lattice(ws[1], "f32")
+    L.step(3)
+    f0 = L.read_populations()
+    L.step(0)
+    assert L.time == 3 and np.array_equal(L.read_populations(), f0)
+
+    B = rl.Batch(ws, "f32")
+    B.step(2)
+    snap = [bl.read_populations() for bl in B.lattices]
+    B.step(0)
+    B.set_active(np.zeros(len(ws), dtype=np.uint8))
+    B.step(5)
+    for k, bl in enumerate(B.lattices):
+        assert bl.time == 2 and np.array_equal(bl.read_populations(), snap[k]), k
+    B.close()
+
+    one = rl.Batch(ws[3:4], "f64")
+    one.step(40, graph=True)
+    ref = gpu_lattice(ws[3], "f64")
+    ref.step(40)
+    assert np.array_equal(one.lattices[0].read_populations(), ref.read_populations())
+    one.close()
