@@ -4,8 +4,8 @@
  * mask, source and drain contact masks, tau and drive planes) to the steady
  * density and velocity fields, trained on steady states the lattice
  * Boltzmann solver itself produces and used to initialise it (the solver
- * stays the judge: a warm start that fails its health check falls back to a
- * cold start).
+ * has the last word: a warm start that fails its health check falls back to
+ * a cold start).
  *
  * Network: NHWC input with cin channels (a multiple of 16; unused channels
  * zero), H and W multiples of 16.  Encoder blocks of two 3x3 convolutions
