@@ -283,7 +283,7 @@ def batch_throughput(storage: str = "f32", count: int = 256, steps: int = 100, w
     for label, graph, tune in (("default_shape_no_graph", False, False), ("default_shape_graph", True, False),
                                ("autotuned_graph", True, True)):
         if tune:
-            B.autotune(10)
+            B.autotune(20)
         B.step(warmup, graph)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)

@@ -270,8 +270,11 @@ typedef struct {
 /* Create a batch of nsamples (>= 1) lattices with one storage, all ordered
  * on one stream (hip_stream, or a stream the batch creates when NULL), and
  * initialise each to its uniform equilibrium.  The samples may differ in
- * size and parameters.  When their populations together outgrow the 256 MB
- * Infinity Cache, every sample starts with streaming stores on. */
+ * size and parameters.  Each sample starts with 256 x 1 tiles when its width
+ * is a multiple of 256, else 64 x 4 (measured on a 256-sample batch of
+ * widths 128..1024: 10% faster than 256 x 1 everywhere).  When their
+ * populations together outgrow the 256 MB Infinity Cache, every sample
+ * starts with streaming stores on. */
 rlbm_status rlbm_batch_create(const rlbm_sample *samples, int nsamples, rlbm_storage storage, void *hip_stream,
                               rlbm_batch **out);
 
@@ -308,10 +311,12 @@ rlbm_status rlbm_batch_residual(rlbm_batch *b, double *r);
 rlbm_status rlbm_batch_step_until(rlbm_batch *b, int64_t max_steps, int64_t check_every, double tol,
                                   int64_t *steps, double *r);
 
-/* Autotuner for the batch: time the batched step with every sample's tile
- * width set to each candidate (64, 128, 256, capped at the sample's interior
- * width), with ordinary and with streaming stores, keep the fastest, restore
- * all states.  ms_per_step: 6 entries or NULL. */
+/* Autotuner for the batch: time the batched step with the samples' shapes
+ * and store forms as they are, then with every sample's tile width set to
+ * each candidate (64, 128, 256, capped at the sample's interior width), with
+ * ordinary and with streaming stores; keep the fastest (the entry setting
+ * unless a candidate is more than 1% faster), restore all states.  ms_per_step: NULL or 6
+ * entries, the candidates' times in that order. */
 rlbm_status rlbm_batch_autotune(rlbm_batch *b, int trial_steps, double *ms_per_step);
 
 /* Item order of the batched kernel, as rlbm_set_block_order: 1 deals each

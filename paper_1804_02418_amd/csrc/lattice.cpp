@@ -942,7 +942,7 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
             break;
         }
         const double per = ms / trial_steps;
-        if (ms_per_step) ms_per_step[c] = per;
+        if (ms_per_step && c >= 0) ms_per_step[c] = per;
         if (per < best) {
             best = per;
             best_tile = tiles[tc];
@@ -1189,6 +1189,10 @@ rlbm_status rlbm_batch_create(const rlbm_sample *samples, int nsamples, rlbm_sto
         st = rlbm_create(q.nx, q.ny, storage, B->stream, &L);
         if (st) break;
         B->lat.push_back(L);
+        // default tiles: 256 x 1 where the width is a whole number of them,
+        // else 64 x 4 (no idle wave at the end of a row, and a block's four
+        // waves pull from four adjacent rows that share source lines in L1)
+        L->shape = q.nx % 256 == 0 ? LaunchShape{256, 1} : LaunchShape{64, 4};
         int nblk_dummy[3];
         if (step_blocks(L, &nblk_dummy[0], &nblk_dummy[1], &nblk_dummy[2]) >= (1 << kItemBlockBits)) {
             st = fail(RLBM_EINVAL, "sample %d is too large for the batched work list", s);
@@ -1393,20 +1397,22 @@ rlbm_status rlbm_batch_autotune(rlbm_batch *B, int trial_steps, double *ms_per_s
     for (int s = 0; s < n; ++s) shape0[s] = B->lat[s]->shape;
     const int tiles[3] = {64, 128, 256};
     double best = INFINITY;
-    int best_c = -1;
+    int best_c = -1;  // -1: the shapes and store forms the samples had on entry
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     rlbm_status st = RLBM_OK;
     std::vector<int> nt0(n);
     for (int s = 0; s < n; ++s) nt0[s] = B->lat[s]->nt_store;
-    for (int c = 0; c < 6 && st == RLBM_OK; ++c) {
-        for (int s = 0; s < n; ++s) {
-            const int w = B->lat[s]->nx;
-            int t = tiles[c % 3];
-            while (t > 64 && t / 2 >= w) t /= 2;
-            B->lat[s]->shape = LaunchShape{t, 256 / t};
-            rlbm_set_streaming_stores(B->lat[s], c / 3);
+    for (int c = -1; c < 6 && st == RLBM_OK; ++c) {
+        if (c >= 0) {
+            for (int s = 0; s < n; ++s) {
+                const int w = B->lat[s]->nx;
+                int t = tiles[c % 3];
+                while (t > 64 && t / 2 >= w) t /= 2;
+                B->lat[s]->shape = LaunchShape{t, 256 / t};
+                rlbm_set_streaming_stores(B->lat[s], c / 3);
+            }
         }
         st = rlbm_batch_step(B, 2, 0);
         if (st) break;
@@ -1418,8 +1424,9 @@ rlbm_status rlbm_batch_autotune(rlbm_batch *B, int trial_steps, double *ms_per_s
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
         const double per = ms / trial_steps;
-        if (ms_per_step) ms_per_step[c] = per;
-        if (per < best) {
+        if (ms_per_step && c >= 0) ms_per_step[c] = per;
+        // leaving the entry setting takes a margin above the trials' noise
+        if (per < (best_c == -1 ? 0.99 * best : best)) {
             best = per;
             best_c = c;
         }
