@@ -46,13 +46,15 @@ struct Mfma<16> {
 
 // ---------------------------------------------------------------- conv 3x3
 
-// grid.x = B * H * ceil(W / 64), grid.y = Co / 16; 4 wavefronts per block,
-// wavefront w covers pixels x0 + 16 w ... + 15 of one row.  The block stages
-// the three input rows it needs (66 pixels: the segment and one on each
-// side, zero outside the image) and its 16 output channels' weights through
-// LDS, 64 input channels at a time, so that every input value is fetched
-// once per block instead of once per tap and wavefront.
-template <int KSTEP, bool RELU>
+// grid.x = B * ceil(H / ROWS) * ceil(W / 64), grid.y = Co / 16; 4
+// wavefronts per block, wavefront w covers pixels x0 + 16 w ... + 15 of
+// ROWS consecutive output rows.  The block stages the ROWS + 2 input rows it
+// needs (66 pixels: the segment and one on each side, zero outside the
+// image) and its 16 output channels' weights through LDS, 64 input channels
+// at a time, so that every input value is fetched once per block instead of
+// once per tap and wavefront, and each staged row serves up to three output
+// rows.
+template <int KSTEP, bool RELU, int ROWS>
 __global__ __launch_bounds__(256) void conv3x3_fwd_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ w,
                                                           const float *__restrict__ bias, bf16 *__restrict__ out,
                                                           int H, int W, int Ci, int Co)
@@ -60,28 +62,31 @@ __global__ __launch_bounds__(256) void conv3x3_fwd_kernel(const bf16 *__restrict
     typedef typename Mfma<KSTEP>::vec vec;
     constexpr int KPL = KSTEP / 4;  // channels per lane per K step
     constexpr int CC = 64, CP = CC + 8;  // channels per chunk, padded row (fewer bank conflicts)
-    __shared__ __attribute__((aligned(16))) bf16 Xs[3][66][CP];
+    __shared__ __attribute__((aligned(16))) bf16 Xs[ROWS + 2][66][CP];
     __shared__ __attribute__((aligned(16))) bf16 Ws[16][9][CP];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int tiles_w = (W + 63) / 64;
+    const int groups_h = (H + ROWS - 1) / ROWS;
     int q = blockIdx.x;
     const int xt = q % tiles_w;
     q /= tiles_w;
-    const int y = q % H;
-    const int b = q / H;
+    const int y0 = (q % groups_h) * ROWS;
+    const int b = q / groups_h;
     const int xs = xt * 64, x0 = xs + wave * 16;
     const int co0 = blockIdx.y * 16;
     const int r = lane & 15;   // A row (pixel) and B column (channel)
     const int kq = lane >> 4;  // which group of KPL channels
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    f32x4 acc[ROWS];
+#pragma unroll
+    for (int rr = 0; rr < ROWS; ++rr) acc[rr] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16 z = (bf16)0.f;
     for (int c0 = 0; c0 < Ci; c0 += CC) {
         const int cc = Ci - c0 < CC ? Ci - c0 : CC;  // a multiple of 16
         const int groups = cc / 8;
-        for (int unit = t; unit < 3 * 66 * groups; unit += 256) {
+        for (int unit = t; unit < (ROWS + 2) * 66 * groups; unit += 256) {
             const int g = unit % groups, rest = unit / groups;
             const int u = rest % 66, rr = rest / 66;
-            const int yy = y + rr - 1, xx = xs + u - 1;
+            const int yy = y0 + rr - 1, xx = xs + u - 1;
             bf16x8 v;
             if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W)
                 v = *reinterpret_cast<const bf16x8 *>(in + (((long long)b * H + yy) * W + xx) * Ci + c0 + 8 * g);
@@ -101,9 +106,12 @@ __global__ __launch_bounds__(256) void conv3x3_fwd_kernel(const bf16 *__restrict
             for (int tap = 0; tap < 9; ++tap) {
                 const int dy = tap / 3, dx = tap % 3;
                 for (int k0 = 0; k0 < cc; k0 += KSTEP) {
-                    const vec a = *reinterpret_cast<const vec *>(&Xs[dy][wave * 16 + r + dx][k0 + kq * KPL]);
                     const vec bv = *reinterpret_cast<const vec *>(&Ws[r][tap][k0 + kq * KPL]);
-                    acc = Mfma<KSTEP>::run(a, bv, acc);
+#pragma unroll
+                    for (int rr = 0; rr < ROWS; ++rr) {
+                        const vec a = *reinterpret_cast<const vec *>(&Xs[rr + dy][wave * 16 + r + dx][k0 + kq * KPL]);
+                        acc[rr] = Mfma<KSTEP>::run(a, bv, acc[rr]);
+                    }
                 }
             }
         }
@@ -113,12 +121,17 @@ __global__ __launch_bounds__(256) void conv3x3_fwd_kernel(const bf16 *__restrict
     const int j = lane & 15;
     const float bj = bias ? bias[co0 + j] : 0.f;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int px = x0 + 4 * (lane >> 4) + s;
-        if (px < W) {
-            float v = acc[s] + bj;
-            if (RELU) v = fmaxf(v, 0.f);
-            out[(((long long)b * H + y) * W + px) * Co + co0 + j] = (bf16)v;
+    for (int rr = 0; rr < ROWS; ++rr) {
+        const int y = y0 + rr;
+        if (y >= H) break;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int px = x0 + 4 * (lane >> 4) + s;
+            if (px < W) {
+                float v = acc[rr][s] + bj;
+                if (RELU) v = fmaxf(v, 0.f);
+                out[(((long long)b * H + y) * W + px) * Co + co0 + j] = (bf16)v;
+            }
         }
     }
 }
@@ -621,19 +634,37 @@ hipError_t conv3x3_forward(const void *in, const void *w, const float *bias, voi
                            int Co, bool relu, hipStream_t s)
 {
     if (Ci % 16 || Co % 16 || B < 1 || H < 1 || W < 1) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(B * H * ((W + 63) / 64)), (unsigned)(Co / 16));
     const bf16 *i = static_cast<const bf16 *>(in), *wt = static_cast<const bf16 *>(w);
     bf16 *o = static_cast<bf16 *>(out);
+    // four output rows per block on images of 32 rows or more (each staged
+    // row then serves up to three output rows), one on the small deep levels
+    // (whose blocks are few already)
+    if (H >= 32) {
+        const dim3 grid((unsigned)(B * ((H + 3) / 4) * ((W + 63) / 64)), (unsigned)(Co / 16));
+        if (Ci % 32 == 0) {
+            if (relu)
+                hipLaunchKernelGGL((conv3x3_fwd_kernel<32, true, 4>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+            else
+                hipLaunchKernelGGL((conv3x3_fwd_kernel<32, false, 4>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+        } else {
+            if (relu)
+                hipLaunchKernelGGL((conv3x3_fwd_kernel<16, true, 4>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+            else
+                hipLaunchKernelGGL((conv3x3_fwd_kernel<16, false, 4>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+        }
+        return hipGetLastError();
+    }
+    const dim3 grid((unsigned)(B * H * ((W + 63) / 64)), (unsigned)(Co / 16));
     if (Ci % 32 == 0) {
         if (relu)
-            hipLaunchKernelGGL((conv3x3_fwd_kernel<32, true>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+            hipLaunchKernelGGL((conv3x3_fwd_kernel<32, true, 1>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
         else
-            hipLaunchKernelGGL((conv3x3_fwd_kernel<32, false>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+            hipLaunchKernelGGL((conv3x3_fwd_kernel<32, false, 1>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
     } else {
         if (relu)
-            hipLaunchKernelGGL((conv3x3_fwd_kernel<16, true>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+            hipLaunchKernelGGL((conv3x3_fwd_kernel<16, true, 1>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
         else
-            hipLaunchKernelGGL((conv3x3_fwd_kernel<16, false>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+            hipLaunchKernelGGL((conv3x3_fwd_kernel<16, false, 1>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
     }
     return hipGetLastError();
 }

@@ -59,11 +59,13 @@ def test_conv3x3_forward_matches_reference(ci, co, relu):
     assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-5 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("ci,co,relu,H,W", [(16, 16, True, 6, 256), (48, 32, False, 5, 200), (32, 16, True, 4, 130)])
+@pytest.mark.parametrize("ci,co,relu,H,W", [(16, 16, True, 6, 256), (48, 32, False, 5, 200), (32, 16, True, 4, 130),
+                                           (16, 16, True, 34, 130), (64, 32, False, 33, 64)])
 def test_conv3x3_forward_wide_images(ci, co, relu, H, W):
     """Images wider than one 64-pixel tile of the forward kernel, also with a
     ragged last tile: the halo between tiles comes from the neighbour's
-    pixels, zero only outside the image."""
+    pixels, zero only outside the image.  From 32 rows on, a block computes
+    four rows (here with a ragged last group of rows)."""
     import paper_1804_02418_amd as rl
 
     torch = _torch()
@@ -83,7 +85,8 @@ def test_conv3x3_forward_wide_images(ci, co, relu, H, W):
 
 
 @pytest.mark.parametrize("ci,co,B,H,W", [(16, 32, 2, 16, 32), (48, 16, 2, 16, 32), (80, 32, 3, 20, 48),
-                                         (128, 16, 2, 160, 16), (16, 16, 1, 6, 256), (32, 16, 2, 3, 200)])
+                                         (128, 16, 2, 160, 16), (16, 16, 1, 6, 256), (32, 16, 2, 3, 200),
+                                         (16, 32, 1, 34, 70)])
 def test_conv3x3_backward_kernels_match_reference(ci, co, B, H, W):
     """Also partial 64-channel blocks, widths that are not a multiple of the
     32-pixel segment, and several row chunks (320 rows of 16 pixels)."""
