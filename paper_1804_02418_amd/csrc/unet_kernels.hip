@@ -50,18 +50,19 @@ struct Mfma<16> {
 // wavefronts per block, wavefront w covers pixels x0 + 16 w ... + 15 of
 // ROWS consecutive output rows.  The block stages the ROWS + 2 input rows it
 // needs (66 pixels: the segment and one on each side, zero outside the
-// image) and its 16 output channels' weights through LDS, 64 input channels
-// at a time, so that every input value is fetched once per block instead of
-// once per tap and wavefront, and each staged row serves up to three output
-// rows.
-template <int KSTEP, bool RELU, int ROWS>
+// image) and its 16 output channels' weights through LDS, CC input channels
+// at a time (16, 32 or 64: the LDS a block holds follows the layer's width,
+// so narrow layers keep more blocks resident), so that every input value is
+// fetched once per block instead of once per tap and wavefront, and each
+// staged row serves up to three output rows.
+template <int KSTEP, bool RELU, int ROWS, int CC>
 __global__ __launch_bounds__(256) void conv3x3_fwd_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ w,
                                                           const float *__restrict__ bias, bf16 *__restrict__ out,
                                                           int H, int W, int Ci, int Co)
 {
     typedef typename Mfma<KSTEP>::vec vec;
     constexpr int KPL = KSTEP / 4;  // channels per lane per K step
-    constexpr int CC = 64, CP = CC + 8;  // channels per chunk, padded row (fewer bank conflicts)
+    constexpr int CP = CC + 8;      // CC channels per chunk, padded row (fewer bank conflicts)
     __shared__ __attribute__((aligned(16))) bf16 Xs[ROWS + 2][66][CP];
     __shared__ __attribute__((aligned(16))) bf16 Ws[16][9][CP];
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
@@ -638,34 +639,39 @@ hipError_t conv3x3_forward(const void *in, const void *w, const float *bias, voi
     bf16 *o = static_cast<bf16 *>(out);
     // four output rows per block on images of 32 rows or more (each staged
     // row then serves up to three output rows), one on the small deep levels
-    // (whose blocks are few already)
-    if (H >= 32) {
-        const dim3 grid((unsigned)(B * ((H + 3) / 4) * ((W + 63) / 64)), (unsigned)(Co / 16));
-        if (Ci % 32 == 0) {
-            if (relu)
-                hipLaunchKernelGGL((conv3x3_fwd_kernel<32, true, 4>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
-            else
-                hipLaunchKernelGGL((conv3x3_fwd_kernel<32, false, 4>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
-        } else {
-            if (relu)
-                hipLaunchKernelGGL((conv3x3_fwd_kernel<16, true, 4>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
-            else
-                hipLaunchKernelGGL((conv3x3_fwd_kernel<16, false, 4>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
-        }
-        return hipGetLastError();
-    }
-    const dim3 grid((unsigned)(B * H * ((W + 63) / 64)), (unsigned)(Co / 16));
-    if (Ci % 32 == 0) {
-        if (relu)
-            hipLaunchKernelGGL((conv3x3_fwd_kernel<32, true, 1>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+    // (whose blocks are few already); channel chunks of the layer's width up
+    // to 64
+    const bool four = H >= 32;
+    const dim3 grid((unsigned)(B * (four ? (H + 3) / 4 : H) * ((W + 63) / 64)), (unsigned)(Co / 16));
+#define RLBM_CONV_FWD(K, R, CC)                                                                                  \
+    do {                                                                                                        \
+        if (relu)                                                                                               \
+            hipLaunchKernelGGL((conv3x3_fwd_kernel<K, true, R, CC>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co); \
+        else                                                                                                    \
+            hipLaunchKernelGGL((conv3x3_fwd_kernel<K, false, R, CC>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co); \
+    } while (0)
+    if (Ci == 16) {
+        if (four)
+            RLBM_CONV_FWD(16, 4, 16);
         else
-            hipLaunchKernelGGL((conv3x3_fwd_kernel<32, false, 1>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+            RLBM_CONV_FWD(16, 1, 16);
+    } else if (Ci == 32) {
+        if (four)
+            RLBM_CONV_FWD(32, 4, 32);
+        else
+            RLBM_CONV_FWD(32, 1, 32);
+    } else if (Ci % 32 == 0) {
+        if (four)
+            RLBM_CONV_FWD(32, 4, 64);
+        else
+            RLBM_CONV_FWD(32, 1, 64);
     } else {
-        if (relu)
-            hipLaunchKernelGGL((conv3x3_fwd_kernel<16, true, 1>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+        if (four)
+            RLBM_CONV_FWD(16, 4, 64);
         else
-            hipLaunchKernelGGL((conv3x3_fwd_kernel<16, false, 1>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co);
+            RLBM_CONV_FWD(16, 1, 64);
     }
+#undef RLBM_CONV_FWD
     return hipGetLastError();
 }
 
