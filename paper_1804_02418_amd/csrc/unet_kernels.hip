@@ -374,22 +374,33 @@ __global__ void relu_backward_kernel(bf16 *__restrict__ d, const bf16 *__restric
 
 // ---------------------------------------------------------------- resampling
 
+// The resampling kernels move 8 channels (16 bytes) per thread: every
+// channel count and channel offset here is a multiple of 8 (the launchers
+// check), so a group never straddles two tensors.  Each element's arithmetic
+// is the same as channel by channel.
+
 // out (B, H/2, W/2, C) = mean of 2x2 blocks of in (B, H, W, C)
 __global__ void pool_fwd_kernel(const bf16 *__restrict__ in, bf16 *__restrict__ out, int B, int H, int W, int C)
 {
-    const int Ho = H / 2, Wo = W / 2;
-    const long long n = (long long)B * Ho * Wo * C;
+    const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+    const long long n = (long long)B * Ho * Wo * C8;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(q % C);
-        long long t = q / C;
+        const int c = 8 * (int)(q % C8);
+        long long t = q / C8;
         const int x = (int)(t % Wo);
         t /= Wo;
         const int y = (int)(t % Ho);
         const int b = (int)(t / Ho);
         const long long base = (((long long)b * H + 2 * y) * W + 2 * x) * C + c;
-        const float s = (float)in[base] + (float)in[base + C] + (float)in[base + (long long)W * C] +
-                        (float)in[base + (long long)W * C + C];
-        out[q] = (bf16)(0.25f * s);
+        const bf16x8 p00 = *reinterpret_cast<const bf16x8 *>(in + base);
+        const bf16x8 p01 = *reinterpret_cast<const bf16x8 *>(in + base + C);
+        const bf16x8 p10 = *reinterpret_cast<const bf16x8 *>(in + base + (long long)W * C);
+        const bf16x8 p11 = *reinterpret_cast<const bf16x8 *>(in + base + (long long)W * C + C);
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            o[e] = (bf16)(0.25f * ((float)p00[e] + (float)p01[e] + (float)p10[e] + (float)p11[e]));
+        *reinterpret_cast<bf16x8 *>(out + 8 * q) = o;
     }
 }
 
@@ -397,35 +408,50 @@ __global__ void pool_fwd_kernel(const bf16 *__restrict__ in, bf16 *__restrict__ 
 __global__ void pool_bwd_kernel(const bf16 *__restrict__ dy, const bf16 *__restrict__ skip, int skip_c, int skip_off,
                                 bf16 *__restrict__ dx, int B, int H, int W, int C)
 {
-    const long long n = (long long)B * H * W * C;
+    const int C8 = C / 8;
+    const long long n = (long long)B * H * W * C8;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(q % C);
-        long long t = q / C;
-        const int x = (int)(t % W);
-        t /= W;
-        const int y = (int)(t % H);
-        const int b = (int)(t / H);
-        float v = 0.25f * (float)dy[(((long long)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
-        if (skip) v += (float)skip[(q / C) * skip_c + skip_off + c];
-        dx[q] = (bf16)v;
-    }
-}
-
-// cat (B, H, W, Cu + Cs): channels [0, Cu) = nearest x2 upsample of u (B, H/2, W/2, Cu),
-// channels [Cu, Cu + Cs) = s (B, H, W, Cs).
-__global__ void up_concat_kernel(const bf16 *__restrict__ u, const bf16 *__restrict__ s, bf16 *__restrict__ cat, int B,
-                                 int H, int W, int Cu, int Cs)
-{
-    const int C = Cu + Cs;
-    const long long n = (long long)B * H * W * C;
-    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(q % C);
-        const long long pix = q / C;
+        const int c = 8 * (int)(q % C8);
+        const long long pix = q / C8;
         const int x = (int)(pix % W);
         const long long t = pix / W;
         const int y = (int)(t % H);
         const int b = (int)(t / H);
-        cat[q] = c < Cu ? u[(((long long)b * (H / 2) + y / 2) * (W / 2) + x / 2) * Cu + c] : s[pix * Cs + (c - Cu)];
+        const bf16x8 g = *reinterpret_cast<const bf16x8 *>(dy + (((long long)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c);
+        bf16x8 k;
+        if (skip) k = *reinterpret_cast<const bf16x8 *>(skip + pix * skip_c + skip_off + c);
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            float v = 0.25f * (float)g[e];
+            if (skip) v += (float)k[e];
+            o[e] = (bf16)v;
+        }
+        *reinterpret_cast<bf16x8 *>(dx + 8 * q) = o;
+    }
+}
+
+// cat (B, H, W, Cu + Cs): channels [0, Cu) = nearest x2 upsample of u (B, H/2, W/2, Cu),
+// channels [Cu, Cu + Cs) = s (B, H, W, Cs)
+__global__ void up_concat_kernel(const bf16 *__restrict__ u, const bf16 *__restrict__ s, bf16 *__restrict__ cat, int B,
+                                 int H, int W, int Cu, int Cs)
+{
+    const int C8 = (Cu + Cs) / 8, Cu8 = Cu / 8;
+    const long long n = (long long)B * H * W * C8;
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const int c8 = (int)(q % C8);
+        const long long pix = q / C8;
+        bf16x8 v;
+        if (c8 < Cu8) {
+            const int x = (int)(pix % W);
+            const long long t = pix / W;
+            const int y = (int)(t % H);
+            const int b = (int)(t / H);
+            v = *reinterpret_cast<const bf16x8 *>(u + (((long long)b * (H / 2) + y / 2) * (W / 2) + x / 2) * Cu + 8 * c8);
+        } else {
+            v = *reinterpret_cast<const bf16x8 *>(s + pix * Cs + 8 * (c8 - Cu8));
+        }
+        *reinterpret_cast<bf16x8 *>(cat + 8 * q) = v;
     }
 }
 
@@ -433,19 +459,24 @@ __global__ void up_concat_kernel(const bf16 *__restrict__ u, const bf16 *__restr
 __global__ void up_bwd_kernel(const bf16 *__restrict__ dcat, bf16 *__restrict__ du, int B, int H, int W, int Cu,
                               int C)
 {
-    const int Ho = H / 2, Wo = W / 2;
-    const long long n = (long long)B * Ho * Wo * Cu;
+    const int Ho = H / 2, Wo = W / 2, Cu8 = Cu / 8;
+    const long long n = (long long)B * Ho * Wo * Cu8;
     for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
-        const int c = (int)(q % Cu);
-        long long t = q / Cu;
+        const int c = 8 * (int)(q % Cu8);
+        long long t = q / Cu8;
         const int x = (int)(t % Wo);
         t /= Wo;
         const int y = (int)(t % Ho);
         const int b = (int)(t / Ho);
         const long long base = (((long long)b * H + 2 * y) * W + 2 * x) * C + c;
-        const float v = (float)dcat[base] + (float)dcat[base + C] + (float)dcat[base + (long long)W * C] +
-                        (float)dcat[base + (long long)W * C + C];
-        du[q] = (bf16)v;
+        const bf16x8 p00 = *reinterpret_cast<const bf16x8 *>(dcat + base);
+        const bf16x8 p01 = *reinterpret_cast<const bf16x8 *>(dcat + base + C);
+        const bf16x8 p10 = *reinterpret_cast<const bf16x8 *>(dcat + base + (long long)W * C);
+        const bf16x8 p11 = *reinterpret_cast<const bf16x8 *>(dcat + base + (long long)W * C + C);
+        bf16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) o[e] = (bf16)((float)p00[e] + (float)p01[e] + (float)p10[e] + (float)p11[e]);
+        *reinterpret_cast<bf16x8 *>(du + 8 * q) = o;
     }
 }
 
@@ -775,7 +806,8 @@ hipError_t relu_backward(void *d, const void *out, long long n, hipStream_t s)
 
 hipError_t pool_forward(const void *in, void *out, int B, int H, int W, int C, hipStream_t s)
 {
-    hipLaunchKernelGGL(pool_fwd_kernel, dim3(grid_for((long long)B * H * W * C / 4)), dim3(256), 0, s,
+    if (C % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pool_fwd_kernel, dim3(grid_for((long long)B * H * W * C / 32)), dim3(256), 0, s,
                        static_cast<const bf16 *>(in), static_cast<bf16 *>(out), B, H, W, C);
     return hipGetLastError();
 }
@@ -783,7 +815,8 @@ hipError_t pool_forward(const void *in, void *out, int B, int H, int W, int C, h
 hipError_t pool_backward(const void *dy, const void *skip, int skip_c, int skip_off, void *dx, int B, int H, int W,
                          int C, hipStream_t s)
 {
-    hipLaunchKernelGGL(pool_bwd_kernel, dim3(grid_for((long long)B * H * W * C)), dim3(256), 0, s,
+    if (C % 8 || (skip && (skip_c % 8 || skip_off % 8))) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pool_bwd_kernel, dim3(grid_for((long long)B * H * W * C / 8)), dim3(256), 0, s,
                        static_cast<const bf16 *>(dy), static_cast<const bf16 *>(skip), skip_c, skip_off,
                        static_cast<bf16 *>(dx), B, H, W, C);
     return hipGetLastError();
@@ -791,7 +824,8 @@ hipError_t pool_backward(const void *dy, const void *skip, int skip_c, int skip_
 
 hipError_t up_concat(const void *u, const void *skip, void *cat, int B, int H, int W, int Cu, int Cs, hipStream_t s)
 {
-    hipLaunchKernelGGL(up_concat_kernel, dim3(grid_for((long long)B * H * W * (Cu + Cs))), dim3(256), 0, s,
+    if (Cu % 8 || Cs % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(up_concat_kernel, dim3(grid_for((long long)B * H * W * (Cu + Cs) / 8)), dim3(256), 0, s,
                        static_cast<const bf16 *>(u), static_cast<const bf16 *>(skip), static_cast<bf16 *>(cat), B, H,
                        W, Cu, Cs);
     return hipGetLastError();
@@ -799,7 +833,8 @@ hipError_t up_concat(const void *u, const void *skip, void *cat, int B, int H, i
 
 hipError_t up_backward(const void *dcat, void *du, int B, int H, int W, int Cu, int C, hipStream_t s)
 {
-    hipLaunchKernelGGL(up_bwd_kernel, dim3(grid_for((long long)B * H * W * Cu / 4)), dim3(256), 0, s,
+    if (Cu % 8 || C % 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(up_bwd_kernel, dim3(grid_for((long long)B * H * W * Cu / 32)), dim3(256), 0, s,
                        static_cast<const bf16 *>(dcat), static_cast<bf16 *>(du), B, H, W, Cu, C);
     return hipGetLastError();
 }
