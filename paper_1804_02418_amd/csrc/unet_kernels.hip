@@ -300,18 +300,32 @@ __global__ __launch_bounds__(256) void channel_sum_part_kernel(bf16 *__restrict_
     float acc[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) acc[e] = 0.f;
-    for (long long p = p0 + r; p < p1; p += rows) {
-        bf16x8 *q = reinterpret_cast<bf16x8 *>(d + p * C + 8 * g);
-        bf16x8 v = *q;
-        if (out) {
-            const bf16x8 o = *reinterpret_cast<const bf16x8 *>(out + p * C + 8 * g);
+    // four pixel rows per pass, all loads issued before any is used; the
+    // additions keep the pixel order p, p + rows, p + 2 rows, ...
+    constexpr int U = 4;
+    for (long long p = p0 + r; p < p1; p += U * rows) {
+        bf16x8 v[U], o[U];
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if (!((float)o[e] > 0.f)) v[e] = (bf16)0.f;
-            *q = v;
+        for (int k = 0; k < U; ++k) {
+            const long long pk = p + (long long)k * rows;
+            if (pk < p1) {
+                v[k] = *reinterpret_cast<const bf16x8 *>(d + pk * C + 8 * g);
+                if (out) o[k] = *reinterpret_cast<const bf16x8 *>(out + pk * C + 8 * g);
+            }
         }
 #pragma unroll
-        for (int e = 0; e < 8; ++e) acc[e] += (float)v[e];
+        for (int k = 0; k < U; ++k) {
+            const long long pk = p + (long long)k * rows;
+            if (pk >= p1) break;
+            if (out) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (!((float)o[k][e] > 0.f)) v[k][e] = (bf16)0.f;
+                *reinterpret_cast<bf16x8 *>(d + pk * C + 8 * g) = v[k];
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[e] += (float)v[k][e];
+        }
     }
     __shared__ float red[256][9];
 #pragma unroll
