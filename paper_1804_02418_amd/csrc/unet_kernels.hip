@@ -153,17 +153,20 @@ __global__ void conv3x3_adjoint_weights_kernel(const bf16 *__restrict__ w, bf16 
 // Weight gradient, one partial per chunk of image rows:
 // part[chunk][co][tap][ci] = sum over the chunk's pixels p of
 //   dpre[p][co] * in[p shifted by tap][ci]   (zero outside the image).
-// A GEMM with M = co, N = ci, K = pixels for each of the 9 taps.  The matrix
-// instructions want 8 consecutive pixels of one channel per lane, while
-// NHWC keeps channels contiguous, so each row segment of SEG pixels is
-// staged through LDS transposed: As[co][px] (16 output channels) and, for
-// CIB input channels and the rows y-1, y, y+1, three copies
-// Bs[dx + 1][ci][row][k] already shifted by the tap's dx, so that every
-// operand is one aligned 16-byte LDS read.  CIB * SEG = 2048 (64 x 32,
-// 32 x 64 or 16 x 128, by the input channel count): the four wavefronts
-// take CIB / 16 channel tiles times SEG / 32 pixel quarters, each keeps the
-// 9 taps' 16 x 16 accumulators, and the quarters of a tile are added in
-// order at the end.
+// A GEMM with M = co, N = ci, K = pixels for each of the 9 taps.  The sum is
+// taken over the input pixel x' = x + dx - 1 of a row:
+//   sum_x' dpre[y][x' + 1 - dx][co] * in[y + dy - 1][x'][ci]
+// (the terms dropped or added at the image edges are zero on either side).
+// The matrix instructions want 8 consecutive pixels of one channel per
+// lane, while NHWC keeps channels contiguous, so each row segment of SEG
+// input pixels is staged through LDS transposed: the CIB input channels of
+// the rows y-1, y, y+1 once, Bs[row][ci][k], and the 16 output channels in
+// three copies shifted by the tap's dx, As[dx][co][k] (a 16-channel tile is
+// cheaper to replicate than CIB channels), so that every operand is one
+// aligned 16-byte LDS read.  CIB * SEG = 2048 (64 x 32, 32 x 64 or 16 x 128,
+// by the input channel count): the four wavefronts take CIB / 16 channel
+// tiles times SEG / 32 pixel quarters, each keeps the 9 taps' 16 x 16
+// accumulators, and the quarters of a tile are added in order at the end.
 // grid.x = chunks (whole rows each), grid.y = (Co / 16) * ceil(Ci / CIB).
 template <int CIB>
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restrict__ dpre,
@@ -171,8 +174,14 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
                                                             int B, int H, int W, int Ci, int Co, int rows_per_chunk)
 {
     constexpr int SEG = 2048 / CIB, NCT = CIB / 16;
-    __shared__ __attribute__((aligned(16))) bf16 As[16][SEG];
-    __shared__ __attribute__((aligned(16))) bf16 Bs[3][CIB][3][SEG];
+    // staging (As then Bs) and, at the end, the reduction of the four waves'
+    // accumulators share one LDS buffer
+    constexpr int kAs = 3 * 16 * SEG, kBs = 3 * CIB * SEG;
+    constexpr int kRed = 4 * 9 * 4 * 64 * (int)sizeof(float);
+    constexpr int kBytes = (kAs + kBs) * (int)sizeof(bf16) > kRed ? (kAs + kBs) * (int)sizeof(bf16) : kRed;
+    __shared__ __attribute__((aligned(16))) char smem[kBytes];
+    bf16 (*As)[16][SEG] = reinterpret_cast<bf16 (*)[16][SEG]>(smem);
+    bf16 (*Bs)[CIB][SEG] = reinterpret_cast<bf16 (*)[CIB][SEG]>(smem + kAs * sizeof(bf16));
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int ct = wave % NCT, kp = wave / NCT;
     const int cib = (Ci + CIB - 1) / CIB;
@@ -191,54 +200,58 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
         const long long img = gr / H;
         for (int x0 = 0; x0 < W; x0 += SEG) {
             const int seg = W - x0 < SEG ? W - x0 : SEG;
-            // ---- stage dpre: SEG pixels x 16 channels, two channels per unit
-            for (int unit = t; unit < SEG * 8; unit += 256) {
-                const int px = unit >> 3, cp = (unit & 7) * 2;
+            // ---- stage dpre: pixels x0-1 .. x0+SEG, 16 channels, two per
+            // unit; pixel x0 + u serves shift dx at k = u - 1 + dx
+            for (int unit = t; unit < (SEG + 2) * 8; unit += 256) {
+                const int u = unit / 8 - 1, cp = (unit % 8) * 2;
+                const int xx = x0 + u;
                 bf16 v0 = z, v1 = z;
-                if (px < seg) {
-                    const bf16 *q = dpre + ((img * H + y) * W + x0 + px) * Co + co0 + cp;
+                if ((unsigned)xx < (unsigned)W) {
+                    const bf16 *q = dpre + ((img * H + y) * W + xx) * Co + co0 + cp;
                     v0 = q[0];
                     v1 = q[1];
                 }
-                As[cp][px] = v0;
-                As[cp + 1][px] = v1;
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const int k = u - 1 + dx;
+                    if (k >= 0 && k < SEG) {
+                        As[dx][cp][k] = v0;
+                        As[dx][cp + 1][k] = v1;
+                    }
+                }
             }
-            // ---- stage in: rows y-1..y+1, pixels x0-1 .. x0+SEG, CIB channels
-            // in groups of 8; the value at pixel x0 + u serves tap dx at k = u - dx
-            for (int unit = t; unit < 3 * (SEG + 2) * (CIB / 8); unit += 256) {
+            // ---- stage in: rows y-1..y+1, pixels x0 .. x0+SEG-1, CIB channels
+            // in groups of 8
+            for (int unit = t; unit < 3 * SEG * (CIB / 8); unit += 256) {
                 const int g = unit % (CIB / 8), rest = unit / (CIB / 8);
-                const int u = rest % (SEG + 2) - 1, rr = rest / (SEG + 2);
-                const int yy = y + rr - 1, xx = x0 + u, c = ci0 + 8 * g;
+                const int k = rest % SEG, rr = rest / SEG;
+                const int yy = y + rr - 1, xx = x0 + k, c = ci0 + 8 * g;
                 bf16x8 v;
-                if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W && c < Ci)
+                if ((unsigned)yy < (unsigned)H && xx < W && c < Ci)
                     v = *reinterpret_cast<const bf16x8 *>(in + ((img * H + yy) * W + xx) * Ci + c);
                 else
                     for (int e = 0; e < 8; ++e) v[e] = z;
 #pragma unroll
-                for (int s2 = 0; s2 < 3; ++s2) {
-                    const int k = u + 1 - s2;
-                    if (k >= 0 && k < SEG) {
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) Bs[s2][8 * g + e][rr][k] = v[e];
-                    }
-                }
+                for (int e = 0; e < 8; ++e) Bs[rr][8 * g + e][k] = v[e];
             }
             __syncthreads();
             if (active && kp * 32 < seg) {
-                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&As[r][kp * 32 + kq * 8]);
+                bf16x8 a[3];
 #pragma unroll
-                for (int tap = 0; tap < 9; ++tap) {
-                    const int dy = tap / 3, dx = tap % 3;
-                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[dx][16 * ct + r][dy][kp * 32 + kq * 8]);
-                    acc[tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[tap], 0, 0, 0);
+                for (int dx = 0; dx < 3; ++dx) a[dx] = *reinterpret_cast<const bf16x8 *>(&As[dx][r][kp * 32 + kq * 8]);
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) {
+                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[dy][16 * ct + r][kp * 32 + kq * 8]);
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx)
+                        acc[dy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[dx], b, acc[dy * 3 + dx], 0, 0, 0);
                 }
             }
             __syncthreads();
         }
     }
     // add the pixel quarters of each channel tile in order, through LDS
-    float *red = reinterpret_cast<float *>(&Bs[0][0][0][0]);  // 4 x 9 x 4 x 64 floats = sizeof(Bs)
-    static_assert(sizeof(Bs) >= 4 * 9 * 4 * 64 * sizeof(float), "reduction space");
+    float *red = reinterpret_cast<float *>(smem);  // 4 x 9 x 4 x 64 floats
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
