@@ -20,7 +20,7 @@ hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part
                                    int Ci, int Co, hipStream_t s);
 // Blocks of the per-channel and head-gradient sums: part needs
 // channel_sum_blocks(npix) * C floats (head_backward: * O * (C + 1)).
-constexpr int kSumBlocks = 1024;
+constexpr int kSumBlocks = 2048;
 int channel_sum_blocks(long long npix);
 // gb[c] += sum_p d[p][c] (deterministic two-pass sum through part when C
 // divides 256, one block per channel otherwise)

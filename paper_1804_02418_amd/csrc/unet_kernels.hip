@@ -806,7 +806,7 @@ hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part
 
 int channel_sum_blocks(long long npix)
 {
-    const long long b = (npix + 1023) / 1024;  // at least 1024 pixels per block
+    const long long b = (npix + 255) / 256;  // at least 256 pixels per block
     return (int)(b < kSumBlocks ? (b < 1 ? 1 : b) : kSumBlocks);
 }
 
