@@ -283,8 +283,19 @@ __global__ __launch_bounds__(256) void reduce_chunks_kernel(const float *__restr
     const int qi = threadIdx.x & 15, grp = threadIdx.x >> 4;
     const long long q = (long long)blockIdx.x * 16 + qi;
     float s = 0.f;
-    if (q < n)
-        for (int c = grp; c < chunks; c += 16) s += part[(long long)c * n + q];
+    if (q < n) {
+        // four chunks' loads in flight per pass, added in chunk order
+        int c = grp;
+        for (; c + 48 < chunks; c += 64) {
+            const float v0 = part[(long long)c * n + q], v1 = part[(long long)(c + 16) * n + q];
+            const float v2 = part[(long long)(c + 32) * n + q], v3 = part[(long long)(c + 48) * n + q];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; c < chunks; c += 16) s += part[(long long)c * n + q];
+    }
     __shared__ float red[16][16];
     red[grp][qi] = s;
     __syncthreads();
