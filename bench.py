@@ -262,13 +262,18 @@ def warm_vs_cold(path: str, count: int = 16, first_index: int = 6000, tol: float
             "speedup_wall": round(t_c / (t_w + t_inf), 3)}
 
 
-def batch_throughput(storage: str = "f32", count: int = 256, steps: int = 100, warmup: int = 10):
+def batch_throughput(storage: str = "f32", count: int = 256, steps: int = 100, warmup: int = 10, rounds: int = 3):
     """Aggregate throughput of the uneven-sample batch (`count` samples of the
     batch generator, about 50 M sites at 256) advanced by the batched kernel,
-    one launch per step over every sample's blocks: default launch shape
-    without and with the step graph, then after the batch autotuner.  HIP
-    events on the batch's stream; the timed call includes the per-call copy
-    of the previous velocities and the field write of its last step."""
+    one launch per step over every sample's blocks: default launch shapes
+    without the step graph, then two batches of the same samples, one with
+    the default shapes and one after the batch autotuner, timed alternately
+    with the step graph for `rounds` rounds (the medians are reported, so
+    that a drift of the clock over the run falls on both alike).  HIP events
+    on the batches' stream; each timed call includes the per-call copy of the
+    previous velocities and the field write of its last step."""
+    import statistics
+
     import torch
 
     import paper_1804_02418_amd as rl
@@ -276,14 +281,10 @@ def batch_throughput(storage: str = "f32", count: int = 256, steps: int = 100, w
 
     # a stream of its own: the batch must not run on a null stream the events would not order
     stream = torch.cuda.Stream()
-    B = rl.Batch(workloads.batch_samples(count), storage, stream=stream.cuda_stream)
-    sites = B.sites()
+    samples = workloads.batch_samples(count)
     per_site = 2 * 48 * BYTES_PER_POP[storage]
-    out = {"samples": count, "sites": sites, "storage": storage, "steps": steps}
-    for label, graph, tune in (("default_shape_no_graph", False, False), ("default_shape_graph", True, False),
-                               ("autotuned_graph", True, True)):
-        if tune:
-            B.autotune(20)
+
+    def timed(B, graph):
         B.step(warmup, graph)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
@@ -292,10 +293,26 @@ def batch_throughput(storage: str = "f32", count: int = 256, steps: int = 100, w
         B.step(steps, graph)
         ev1.record(stream)
         torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / steps
-        out[label] = {"ms_per_step": round(ms, 4), "mlups": round(sites / (ms / 1e3) / 1e6, 1),
-                      "roofline_frac": round(sites * per_site / (ms / 1e3) / (PEAK_HBM_GBS * 1e9), 4)}
-    B.close()
+        return ev0.elapsed_time(ev1) / steps
+
+    def entry(ms):
+        return {"ms_per_step": round(ms, 4), "mlups": round(sites / (ms / 1e3) / 1e6, 1),
+                "roofline_frac": round(sites * per_site / (ms / 1e3) / (PEAK_HBM_GBS * 1e9), 4)}
+
+    default = rl.Batch(samples, storage, stream=stream.cuda_stream)
+    sites = default.sites()
+    out = {"samples": count, "sites": sites, "storage": storage, "steps": steps, "rounds": rounds}
+    out["default_shape_no_graph"] = entry(timed(default, False))
+    tuned = rl.Batch(samples, storage, stream=stream.cuda_stream)
+    tuned.autotune(20)
+    t_default, t_tuned = [], []
+    for _ in range(rounds):
+        t_default.append(timed(default, True))
+        t_tuned.append(timed(tuned, True))
+    out["default_shape_graph"] = entry(statistics.median(t_default))
+    out["autotuned_graph"] = entry(statistics.median(t_tuned))
+    default.close()
+    tuned.close()
     return out
 
 
