@@ -730,11 +730,11 @@ hipError_t conv3x3_forward(const void *in, const void *w, const float *bias, voi
     if (Ci % 16 || Co % 16 || B < 1 || H < 1 || W < 1) return hipErrorInvalidValue;
     const bf16 *i = static_cast<const bf16 *>(in), *wt = static_cast<const bf16 *>(w);
     bf16 *o = static_cast<bf16 *>(out);
-    // four output rows per block on images of 32 rows or more (each staged
-    // row then serves up to three output rows), one on the small deep levels
-    // (whose blocks are few already); channel chunks of the layer's width up
-    // to 64
-    const bool four = H >= 32;
+    // four output rows per block on images of 16 rows or more (each staged
+    // row then serves up to three output rows; measured faster than one row
+    // per block down to the 16 x 16 level of a 256 x 256 network), one on
+    // smaller images; channel chunks of the layer's width up to 64
+    const bool four = H >= 16;
     const dim3 grid((unsigned)(B * (four ? (H + 3) / 4 : H) * ((W + 63) / 64)), (unsigned)(Co / 16));
 #define RLBM_CONV_FWD(K, R, CC)                                                                                  \
     do {                                                                                                        \

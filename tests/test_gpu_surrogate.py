@@ -64,7 +64,7 @@ def test_conv3x3_forward_matches_reference(ci, co, relu):
 def test_conv3x3_forward_wide_images(ci, co, relu, H, W):
     """Images wider than one 64-pixel tile of the forward kernel, also with a
     ragged last tile: the halo between tiles comes from the neighbour's
-    pixels, zero only outside the image.  From 32 rows on, a block computes
+    pixels, zero only outside the image.  From 16 rows on, a block computes
     four rows (here with a ragged last group of rows)."""
     import paper_1804_02418_amd as rl
 
