@@ -46,7 +46,8 @@ struct rlbm_unet {
     long long nparam = 0;
     float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
     void *theta_bf = nullptr;
-    void *wt = nullptr;
+    void *wt = nullptr;  // adjoint weights of every 3x3 layer, back to back (adj.toff)
+    AdjointTable adj{};
     float *part = nullptr;
     double *mse_part = nullptr;
     int mse_blocks = 256;
@@ -166,9 +167,10 @@ rlbm_status conv_bwd(rlbm_unet *N, int i, int B, bool want_input)
     UTRY(conv3x3_backward_weight(N->gact[i], layer_input(N, i), N->part, N->grad + l.woff, B, h, w, l.ci, l.co,
                                  N->stream));
     if (want_input) {
-        const char *wbf = static_cast<const char *>(N->theta_bf) + 2 * l.woff;
-        UTRY(conv3x3_adjoint_weights(wbf, N->wt, l.ci, l.co, N->stream));
-        UTRY(conv3x3_forward(N->gact[i], N->wt, nullptr, layer_input_grad(N, i), B, h, w, l.co, l.ci, false,
+        // the adjoint weights of every layer were formed at the start of the
+        // backward pass; layer i is entry i (every layer before the head is 3 x 3)
+        const void *wt = static_cast<const char *>(N->wt) + 2 * N->adj.toff[i];
+        UTRY(conv3x3_forward(N->gact[i], wt, nullptr, layer_input_grad(N, i), B, h, w, l.co, l.ci, false,
                              N->stream));
     }
     return RLBM_OK;
@@ -245,10 +247,21 @@ rlbm_status rlbm_unet_create(int base, int cin, int cout, int height, int width,
     alloc((void **)&N->m, P * 4);
     alloc((void **)&N->v, P * 4);
     alloc(&N->theta_bf, P * 2);
-    size_t wt_max = 0, part_max = 0;
+    size_t part_max = 0;
+    // the 3x3 layers' adjoint weights, back to back in layer order
+    N->adj.n = 0;
+    N->adj.toff[0] = 0;
     for (int i = 0; i < NLAYER; ++i) {
         const Layer &l = N->L[i];
-        wt_max = std::max(wt_max, (size_t)l.co * 9 * l.ci);
+        if (l.k != 3) continue;
+        N->adj.woff[N->adj.n] = l.woff;
+        N->adj.ci[N->adj.n] = l.ci;
+        N->adj.co[N->adj.n] = l.co;
+        N->adj.toff[N->adj.n + 1] = N->adj.toff[N->adj.n] + (long long)l.co * 9 * l.ci;
+        ++N->adj.n;
+    }
+    for (int i = 0; i < NLAYER; ++i) {
+        const Layer &l = N->L[i];
         const long long np = (long long)px(N, l.level, max_batch);
         if (l.k == 3)
             part_max = std::max(part_max, (size_t)conv3x3_wgrad_chunks(max_batch, N->lh(l.level), N->lw(l.level), l.ci, l.co) *
@@ -258,7 +271,7 @@ rlbm_status rlbm_unet_create(int base, int cin, int cout, int height, int width,
         alloc(&N->act[i], px(N, l.level, max_batch) * l.co * 2);
         alloc(&N->gact[i], px(N, l.level, max_batch) * l.co * 2);
     }
-    alloc(&N->wt, wt_max * 2);
+    alloc(&N->wt, (size_t)N->adj.toff[N->adj.n] * 2);
     alloc((void **)&N->part, part_max * 4);
     alloc((void **)&N->mse_part, N->mse_blocks * 8);
     alloc(&N->x, px(N, 0, max_batch) * cin * 2);
@@ -388,6 +401,7 @@ rlbm_status rlbm_unet_backward(rlbm_unet *N, const float *dy, int batch, float *
     const int B = batch;
     const int c0 = N->base, c1 = 2 * c0, c2 = 4 * c0, c3 = 8 * c0;
     const Layer &h = N->L[HEAD];
+    UTRY(conv3x3_adjoint_weights_all(N->theta_bf, N->wt, N->adj, N->stream));
     UTRY(head_backward(dy, N->act[D1B], static_cast<const char *>(N->theta_bf) + 2 * h.woff, N->gact[D1B], N->part,
                        N->grad + h.woff, N->grad + h.boff, (long long)px(N, 0, B), h.ci, h.co, N->stream));
     rlbm_status st;

@@ -12,6 +12,16 @@ hipError_t conv3x3_forward(const void *in, const void *w, const float *bias, voi
 // wt[ci][8 - tap][co] = w[co][tap][ci]; the gradient with respect to the input of a 3x3
 // convolution is conv3x3_forward(dout, wt) (no bias, no activation).
 hipError_t conv3x3_adjoint_weights(const void *w, void *wt, int Ci, int Co, hipStream_t s);
+// The same for up to kMaxAdjoint layers in one launch: layer k's weights at
+// element w + woff[k] (Co x 9 x Ci) go transposed to element wt + toff[k];
+// the layers lie back to back in wt (toff[k + 1] = toff[k] + Co 9 Ci).
+constexpr int kMaxAdjoint = 32;
+struct AdjointTable {
+    int n;
+    long long woff[kMaxAdjoint], toff[kMaxAdjoint + 1];
+    int ci[kMaxAdjoint], co[kMaxAdjoint];
+};
+hipError_t conv3x3_adjoint_weights_all(const void *w, void *wt, const AdjointTable &t, hipStream_t s);
 // Weight-gradient partials (chunks of whole image rows); part needs
 // conv3x3_wgrad_chunks(B, H, W, Ci, Co) * Co * 9 * Ci floats.
 int conv3x3_wgrad_chunks(int B, int H, int W, int Ci, int Co);

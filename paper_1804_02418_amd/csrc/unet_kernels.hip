@@ -150,6 +150,23 @@ __global__ void conv3x3_adjoint_weights_kernel(const bf16 *__restrict__ w, bf16 
     }
 }
 
+// All layers' adjoint weights in one launch (one thread per source weight;
+// the layer is found by a scan of the table's offsets).
+__global__ void conv3x3_adjoint_all_kernel(const bf16 *__restrict__ w, bf16 *__restrict__ wt, const AdjointTable t)
+{
+    const long long n = t.toff[t.n];
+    for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        int k = 0;
+        while (k + 1 < t.n && q >= t.toff[k + 1]) ++k;
+        const long long local = q - t.toff[k];
+        const int Ci = t.ci[k], Co = t.co[k];
+        const int ci = (int)(local % Ci);
+        const int tap = (int)((local / Ci) % 9);
+        const int co = (int)(local / ((long long)Ci * 9));
+        wt[t.toff[k] + ((long long)ci * 9 + (8 - tap)) * Co + co] = w[t.woff[k] + local];
+    }
+}
+
 // Weight gradient, one partial per chunk of image rows:
 // part[chunk][co][tap][ci] = sum over the chunk's pixels p of
 //   dpre[p][co] * in[p shifted by tap][ci]   (zero outside the image).
@@ -765,6 +782,14 @@ hipError_t conv3x3_forward(const void *in, const void *w, const float *bias, voi
             RLBM_CONV_FWD(16, 1, 64);
     }
 #undef RLBM_CONV_FWD
+    return hipGetLastError();
+}
+
+hipError_t conv3x3_adjoint_weights_all(const void *w, void *wt, const AdjointTable &t, hipStream_t s)
+{
+    if (t.n < 1 || t.n > kMaxAdjoint) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(conv3x3_adjoint_all_kernel, dim3(grid_for(t.toff[t.n])), dim3(256), 0, s,
+                       static_cast<const bf16 *>(w), static_cast<bf16 *>(wt), t);
     return hipGetLastError();
 }
 
