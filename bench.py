@@ -111,6 +111,7 @@ def cpu_baseline(w, steps: int):
     t0 = time.perf_counter()
     O.run(steps)
     dt = time.perf_counter() - t0
+    ref = O.fields()
     # the same oracle on one thread, over a twentieth of the steps
     s1 = max(1, steps // 20)
     lib.orc_set_threads(1)
@@ -118,11 +119,35 @@ def cpu_baseline(w, steps: int):
     O.run(s1)
     d1 = time.perf_counter() - t1
     lib.orc_set_threads(cores)
-    return {"value": w["nx"] * w["ny"] * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+    base = {"value": w["nx"] * w["ny"] * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{w['nx']}x{w['ny']} graphene sample, {steps} steps from the uniform start, FP64, "
                       f"{dt:.1f} s",
             "single_thread": {"value": w["nx"] * w["ny"] * s1 / d1 / 1e6, "unit": "MLUPS",
                               "sample": f"the next {s1} steps, {d1:.1f} s"}}
+    return base, ref
+
+
+def errors_vs_oracle(w, steps: int, ref):
+    """The library's step in every storage, `steps` steps from the same
+    uniform start as the oracle's fields `ref`: max-relative error in n (per
+    site) and in u (of the largest oracle velocity) over the fluid sites."""
+    import numpy as np
+    import torch
+
+    fluid = ~w["mask"].astype(bool) if w.get("mask") is not None else np.ones((w["ny"], w["nx"]), bool)
+    rn = ref["n"][fluid]
+    ru = np.hypot(ref["vx"], ref["vy"])[fluid]
+    out = {"steps": steps, "reference": "FP64 oracle"}
+    for st in ("f64", "f32", "f16dev"):
+        L = make_lattice(w, st, torch.cuda.current_stream().cuda_stream)
+        L.step(steps)
+        g = L.read_fields()
+        L.close()
+        du = np.hypot(g["vx"] - ref["vx"], g["vy"] - ref["vy"])[fluid]
+        out[st] = {"err_n": float(np.max(np.abs(g["n"][fluid] - rn) / np.abs(rn))),
+                   "err_u": float(du.max() / ru.max())}
+    out["max_u"] = float(ru.max())
+    return out
 
 
 def copy_calibration(nbytes: int, reps: int = 20):
@@ -467,7 +492,8 @@ def main(argv=None):
     if not args.no_warm_start and os.path.exists(WEIGHTS):
         out["time_to_steady"] = warm_vs_cold(WEIGHTS)
     if args.cpu_steps > 0:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        out["cpu_baseline"], ref = cpu_baseline(w, args.cpu_steps)
+        out["errors_vs_oracle"] = errors_vs_oracle(w, args.cpu_steps, ref)
     print(json.dumps(out), flush=True)
     return 0
 
