@@ -130,6 +130,25 @@ def test_graphene_sample_full_size_one_step_from_gpu_state():
     G.close()
 
 
+def test_graphene_sample_full_size_200_steps_matches_oracle():
+    """1024 x 512 graphene sample, FP64, 200 steps on both sides from the
+    uniform start.  n holds 1e-12 relative.  The velocity stays below 4e-4
+    here, and rounding-order differences of a few units in the last place of
+    the unit-scale four-velocity remain; u is held to 1e-13 absolute."""
+    w = workloads.graphene_sample(storage="f64")
+    O = oracle_lattice(w)
+    G = gpu_lattice(w, "f64")
+    O.run(200)
+    G.step(200)
+    ref = O.fields()
+    got = G.read_fields()
+    G.close()
+    e = field_errors(got, ref)
+    du = float(np.max(np.hypot(got["vx"] - ref["vx"], got["vy"] - ref["vy"])))
+    _say("graphene 1024x512 200 steps", e, "abs u", du)
+    assert e["err_n"] <= TOL and e["err_eps"] <= TOL and du <= 1e-13
+
+
 def test_checkpoint_restore_is_bit_identical():
     w = workloads.small_device(nx=96, ny=40, steps=20)
     G = gpu_lattice(w, "f64")
