@@ -30,7 +30,7 @@ sys.path.insert(0, HERE)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 BYTES_PER_POP = {"f64": 8, "f32": 4, "f16dev": 2}
-KERNEL_SOURCES = ["paper_1804_02418_amd/csrc/step_kernels.hip", "paper_1804_02418_amd/csrc/rlbm_math.h",
+KERNEL_SOURCES = ["paper_1804_02418_amd/csrc/step_impl.h", "paper_1804_02418_amd/csrc/rlbm_math.h",
                   "paper_1804_02418_amd/csrc/rlbm_kernels.h"]
 
 
