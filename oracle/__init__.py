@@ -28,30 +28,41 @@ from . import appendix, quadrature
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rlbm_oracle.c")
 _LIB = os.path.join(_HERE, "librlbm_oracle.so")
+# The same source built with long double arithmetic and state (-DORC_LONG_DOUBLE):
+# the same discrete problem with about 2^-11 of the rounding error, used to
+# measure the rounding floor of the float64 build.
+_LIB_LD = os.path.join(_HERE, "librlbm_oracle_ld.so")
 
 Q = quadrature.Q
 K = 16
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, long_double: bool = False) -> str:
     """Compile the plain-C oracle (gcc, -O2, OpenMP).  Returns the .so path."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+    out = _LIB_LD if long_double else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
         subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-                        "-o", tmp, _SRC, "-lm"], check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+                        *(["-DORC_LONG_DOUBLE"] if long_double else []), "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, out)
+    return out
 
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
+_ldp = ctypes.POINTER(ctypes.c_longdouble)
 
 
-@functools.lru_cache(maxsize=1)
-def lib() -> ctypes.CDLL:
-    path = build(force=False)
+@functools.lru_cache(maxsize=2)
+def lib(long_double: bool = False) -> ctypes.CDLL:
+    path = build(force=False, long_double=long_double)
     L = ctypes.CDLL(path)
     vp = ctypes.c_void_p
+    rp = _ldp if long_double else _dp          # pointer to the arithmetic type
+    rv = ctypes.c_longdouble if long_double else ctypes.c_double
+    L.orc_real_bytes.restype = ctypes.c_int
+    if L.orc_real_bytes() != ctypes.sizeof(rv):
+        raise RuntimeError(f"{path}: built for another arithmetic type")
     L.orc_stencil_new.restype = vp
     L.orc_stencil_new.argtypes = [_dp, _dp, _dp, _dp, _ip, _ip, _ip, _dp, _dp, _dp]
     L.orc_stencil_free.argtypes = [vp]
@@ -59,30 +70,29 @@ def lib() -> ctypes.CDLL:
     L.orc_set_threads.restype = None
     L.orc_get_threads.argtypes = []
     L.orc_get_threads.restype = ctypes.c_int
-    L.orc_projections.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp]
-    L.orc_moments.argtypes = [vp, _dp, _dp, _dp]
-    L.orc_landau.argtypes = [_dp, _dp, _dp]
+    L.orc_projections.argtypes = [rv, rv, rp, rp]
+    L.orc_moments.argtypes = [vp, rp, rp, rp]
+    L.orc_landau.argtypes = [rp, rp, rp]
     L.orc_landau.restype = ctypes.c_int
-    L.orc_macro.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_macro.argtypes = [vp, rp, rp, rp, rp, rp]
     L.orc_macro.restype = ctypes.c_int
-    L.orc_feq.argtypes = [vp, ctypes.c_double, ctypes.c_double, _dp, _dp]
-    L.orc_force_term.argtypes = [vp, ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double,
-                                 ctypes.c_double, _dp]
-    L.orc_collide.argtypes = [vp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+    L.orc_feq.argtypes = [vp, rv, rv, rp, rp]
+    L.orc_force_term.argtypes = [vp, rv, rv, rp, rv, rv, rp]
+    L.orc_collide.argtypes = [vp, rp, rv, rv, rv, rp]
     L.orc_collide.restype = ctypes.c_int
     L.orc_lattice_new.restype = vp
     L.orc_lattice_new.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_int, _ip, _ip, _ip, _dp, ctypes.c_void_p,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_double]
     L.orc_lattice_free.argtypes = [vp]
-    L.orc_lattice_collide.argtypes = [vp, _dp, _dp]
+    L.orc_lattice_collide.argtypes = [vp, rp, rp]
     L.orc_lattice_collide.restype = ctypes.c_int
-    L.orc_lattice_stream.argtypes = [vp, _dp, _dp]
-    L.orc_lattice_run.argtypes = [vp, _dp, ctypes.c_int64]
+    L.orc_lattice_stream.argtypes = [vp, rp, rp]
+    L.orc_lattice_run.argtypes = [vp, rp, ctypes.c_int64]
     L.orc_lattice_run.restype = ctypes.c_int
-    L.orc_lattice_fields.argtypes = [vp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_lattice_fields.argtypes = [vp, rp, rp, rp, rp, rp, rp]
     L.orc_lattice_fields.restype = ctypes.c_int
-    L.orc_lattice_init.argtypes = [vp, _dp, _dp, _dp, _dp, _dp]
+    L.orc_lattice_init.argtypes = [vp, _dp, _dp, _dp, _dp, rp]
     L.orc_lattice_set_lca.argtypes = [vp, ctypes.c_double]
     return L
 
@@ -92,17 +102,33 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(_dp)
 
 
+def _rptr(a: np.ndarray):
+    """Pointer to a float64 or long double array (the arithmetic type of a build)."""
+    assert a.flags.c_contiguous
+    if a.dtype == np.float64:
+        return a.ctypes.data_as(_dp)
+    assert a.dtype == np.longdouble
+    return a.ctypes.data_as(_ldp)
+
+
 def _iptr(a: np.ndarray):
     assert a.dtype == np.int32 and a.flags.c_contiguous
     return a.ctypes.data_as(_ip)
 
 
 class Stencil:
-    """The 48-node quadrature with its Appendix A table and force matrices."""
+    """The 48-node quadrature with its Appendix A table and force matrices.
 
-    def __init__(self, use_printed: bool = False, shells=None):
+    long_double: use the long double build of the oracle (state, fields and
+    per-site arguments are numpy.longdouble arrays) on the same float64
+    constants."""
+
+    def __init__(self, use_printed: bool = False, shells=None, long_double: bool = False):
         nodes = quadrature.node_table(use_printed, shells)
         self.nodes = nodes
+        self.long_double = bool(long_double)
+        self.real = np.longdouble if long_double else np.float64
+        self._lib = lib(self.long_double)
         self.w = np.array(nodes["w"], dtype=np.float64)
         self.p0 = np.array(nodes["p0"], dtype=np.float64)
         self.px = np.array(nodes["px"], dtype=np.float64)
@@ -114,50 +140,53 @@ class Stencil:
         Cx, Cy = appendix.force_matrices()
         self.Cx = np.ascontiguousarray(Cx)
         self.Cy = np.ascontiguousarray(Cy)
-        self._h = lib().orc_stencil_new(_ptr(self.w), _ptr(self.p0), _ptr(self.px), _ptr(self.py),
-                                        _iptr(self.cx), _iptr(self.cy), _iptr(self.opp),
-                                        _ptr(self.J), _ptr(self.Cx), _ptr(self.Cy))
+        self._h = self._lib.orc_stencil_new(_ptr(self.w), _ptr(self.p0), _ptr(self.px), _ptr(self.py),
+                                            _iptr(self.cx), _iptr(self.cy), _iptr(self.opp),
+                                            _ptr(self.J), _ptr(self.Cx), _ptr(self.Cy))
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_stencil_free(h)
+            self._lib.orc_stencil_free(h)
             self._h = None
+
+    def _arr(self, a):
+        return np.ascontiguousarray(a, dtype=self.real)
 
     # ---- per-site operations (each a thin call into the C oracle) ----
     def moments(self, f):
-        f = np.ascontiguousarray(f, dtype=np.float64)
-        N = np.zeros(3)
-        T = np.zeros(9)
-        lib().orc_moments(self._h, _ptr(f), _ptr(N), _ptr(T))
+        f = self._arr(f)
+        N = np.zeros(3, dtype=self.real)
+        T = np.zeros(9, dtype=self.real)
+        self._lib.orc_moments(self._h, _rptr(f), _rptr(N), _rptr(T))
         return N, T.reshape(3, 3)
 
     def macro(self, f):
         """(n, T, eps, U) of one site's populations."""
-        f = np.ascontiguousarray(f, dtype=np.float64)
-        out = np.zeros(3)
-        U = np.zeros(3)
-        rc = lib().orc_macro(self._h, _ptr(f), _ptr(out[0:1]), _ptr(out[1:2]), _ptr(out[2:3]), _ptr(U))
+        f = self._arr(f)
+        out = np.zeros(3, dtype=self.real)
+        U = np.zeros(3, dtype=self.real)
+        rc = self._lib.orc_macro(self._h, _rptr(f), _rptr(out[0:1]), _rptr(out[1:2]), _rptr(out[2:3]), _rptr(U))
         if rc:
             raise ArithmeticError("no timelike Landau eigenvector")
         return out[0], out[1], out[2], U
 
     def feq(self, n, T, U):
-        U = np.ascontiguousarray(U, dtype=np.float64)
-        out = np.zeros(Q)
-        lib().orc_feq(self._h, float(n), float(T), _ptr(U), _ptr(out))
+        U = self._arr(U)
+        out = np.zeros(Q, dtype=self.real)
+        self._lib.orc_feq(self._h, n, T, _rptr(U), _rptr(out))
         return out
 
     def force_term(self, n, T, U, Fx, Fy):
-        U = np.ascontiguousarray(U, dtype=np.float64)
-        out = np.zeros(Q)
-        lib().orc_force_term(self._h, float(n), float(T), _ptr(U), float(Fx), float(Fy), _ptr(out))
+        U = self._arr(U)
+        out = np.zeros(Q, dtype=self.real)
+        self._lib.orc_force_term(self._h, n, T, _rptr(U), Fx, Fy, _rptr(out))
         return out
 
     def collide(self, f, tau, Fx=0.0, Fy=0.0):
-        f = np.ascontiguousarray(f, dtype=np.float64)
-        out = np.zeros(Q)
-        if lib().orc_collide(self._h, _ptr(f), float(tau), float(Fx), float(Fy), _ptr(out)):
+        f = self._arr(f)
+        out = np.zeros(Q, dtype=self.real)
+        if self._lib.orc_collide(self._h, _rptr(f), tau, Fx, Fy, _rptr(out)):
             raise ArithmeticError("collision failed (no Landau frame)")
         return out
 
@@ -190,7 +219,8 @@ EDGES = {"bottom": 0, "top": 1, "left": 2, "right": 3}
 
 
 class Lattice:
-    """nx x ny lattice holding the pre-collision populations f (SoA, float64).
+    """nx x ny lattice holding the pre-collision populations f (SoA, float64,
+    or long double with a long double stencil).
 
     contacts: iterable of dicts {edge, start, width, n, T, vx, vy}; edge is
     'bottom' | 'top' | 'left' | 'right' (or 0..3).  Non-periodic edges are
@@ -215,47 +245,56 @@ class Lattice:
         if solid is not None:
             self._solid = np.ascontiguousarray(solid, dtype=np.uint8).reshape(self.ny, self.nx)
             sp = self._solid.ctypes.data_as(ctypes.c_void_p)
-        self._h = lib().orc_lattice_new(stencil._h, self.nx, self.ny, int(periodic_x), int(periodic_y),
-                                        len(contacts), _iptr(edge), _iptr(start), _iptr(width),
-                                        _ptr(state), sp, self.tau, self.F[0], self.F[1])
+        self._lib = stencil._lib
+        self._h = self._lib.orc_lattice_new(stencil._h, self.nx, self.ny, int(periodic_x), int(periodic_y),
+                                            len(contacts), _iptr(edge), _iptr(start), _iptr(width),
+                                            _ptr(state), sp, self.tau, self.F[0], self.F[1])
         if not self._h:
             raise ValueError("invalid lattice description")
         # local-capacitance force -(1/C_g) grad n (None or inf: off)
         if cg is not None and np.isfinite(cg):
-            lib().orc_lattice_set_lca(self._h, 1.0 / float(cg))
-        self.f = np.zeros((Q, self.ny, self.nx), dtype=np.float64)
+            self._lib.orc_lattice_set_lca(self._h, 1.0 / float(cg))
+        self.f = np.zeros((Q, self.ny, self.nx), dtype=stencil.real)
         self.t = 0
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_lattice_free(h)
+            self._lib.orc_lattice_free(h)
             self._h = None
 
     def init_fields(self, n, T, vx, vy):
         shape = (self.ny, self.nx)
         arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(a, dtype=np.float64), shape))
                 for a in (n, T, vx, vy)]
-        lib().orc_lattice_init(self._h, *[_ptr(a) for a in arrs], _ptr(self.f))
+        self._lib.orc_lattice_init(self._h, *[_ptr(a) for a in arrs], _rptr(self.f))
         self.t = 0
 
     def run(self, nsteps: int) -> None:
-        bad = lib().orc_lattice_run(self._h, _ptr(self.f), int(nsteps))
+        bad = self._lib.orc_lattice_run(self._h, _rptr(self.f), int(nsteps))
         self.t += int(nsteps)
         if bad:
             raise ArithmeticError(f"{bad} site updates without a Landau frame")
 
     def post_collision(self) -> np.ndarray:
         out = np.empty_like(self.f)
-        if lib().orc_lattice_collide(self._h, _ptr(self.f), _ptr(out)):
+        if self._lib.orc_lattice_collide(self._h, _rptr(self.f), _rptr(out)):
             raise ArithmeticError("collision failed")
         return out
 
     def fields(self):
         """dict of n, vx, vy, eps, T arrays (ny, nx) of the current state."""
-        out = {k: np.empty((self.ny, self.nx)) for k in ("n", "vx", "vy", "eps", "T")}
-        lib().orc_lattice_fields(self._h, _ptr(self.f), _ptr(out["n"]), _ptr(out["vx"]),
-                                 _ptr(out["vy"]), _ptr(out["eps"]), _ptr(out["T"]))
+        out = {k: np.empty((self.ny, self.nx), dtype=self.st.real) for k in ("n", "vx", "vy", "eps", "T")}
+        self._lib.orc_lattice_fields(self._h, _rptr(self.f), _rptr(out["n"]), _rptr(out["vx"]),
+                                     _rptr(out["vy"]), _rptr(out["eps"]), _rptr(out["T"]))
+        return out
+
+    def stream(self, fstar: np.ndarray) -> np.ndarray:
+        """Streaming with the boundary rules alone: the pre-collision state
+        that the post-collision populations fstar (Q, ny, nx) lead to."""
+        fstar = np.ascontiguousarray(fstar, dtype=self.st.real)
+        out = np.empty_like(fstar)
+        self._lib.orc_lattice_stream(self._h, _rptr(fstar), _rptr(out))
         return out
 
     def totals(self):
@@ -270,6 +309,6 @@ class Lattice:
         }
 
 
-@functools.lru_cache(maxsize=2)
-def stencil(use_printed: bool = False) -> Stencil:
-    return Stencil(use_printed)
+@functools.lru_cache(maxsize=4)
+def stencil(use_printed: bool = False, long_double: bool = False) -> Stencil:
+    return Stencil(use_printed, long_double=long_double)

@@ -6,7 +6,11 @@
   one.
 * Closed box (bounce-back walls): global N^0 and T^00 are constant.
 * Contacts: the change of global N^0 equals the flux through the contact
-  ghost spans (bookkeeping written out independently below).
+  ghost spans (bookkeeping written out independently below), on every edge
+  and with spans that reach the corners.
+* Solid masks: a closed box with an interior obstacle keeps N^0 and T^00.
+* A quarter turn of the whole problem gives the turned flow (ties the four
+  edges' boundary handling together); corner sources bounce back.
 * Shear viscosity nu = 6.25 (tau - 1/2) sites^2/step (eta = 3/4 n T
   (tau - 1/2); the paper's remark eta = 3/8 at n = T = tau = 1).
 * Sound speed c/sqrt(2) = 5/sqrt(2) sites/step (massless 2-D gas, eps = 2P).
@@ -199,3 +203,203 @@ def test_channel_flow_curvature():
     c2 = np.polyfit(yy[core], vx[core], 2)[0]
     expected = -F / (3 * 1.0 * nu) / 2
     assert abs(c2 / expected - 1) < 0.02, (c2, expected)
+
+
+# ---- solid masks, side contacts and corners (Sec. 3, Fig. `geom` caption;
+# readings R11 and R12: bounce-back from solid or off-lattice sources,
+# contacts as ghost spans, corner sources are walls) ----
+
+def test_closed_box_with_solid_block_conserves_number_and_energy():
+    """Bounce-back from solid sites is an on-site reversal (R11): every
+    post-collision population lands exactly once, so a closed box with an
+    interior obstacle keeps global N^0 and T^00 to round-off."""
+    nx, ny = 29, 21
+    solid = np.zeros((ny, nx), dtype=np.uint8)
+    solid[7:13, 9:15] = 1          # a block thicker than one hop
+    solid[3, 20:27] = 1            # a one-site-thick wall that hops jump over
+    L = oracle.Lattice(_st(), nx, ny, solid=solid, tau=0.7)
+    n, T, vx, vy = _smooth_fields(nx, ny, amp=3e-2)
+    L.init_fields(n, T, vx + 0.02, vy)
+    fluid = solid == 0
+
+    def tot():
+        f = L.f[:, fluid]
+        return float(_st().p0 @ f.sum(axis=1)), float((_st().p0 ** 2) @ f.sum(axis=1))
+
+    n0, e0 = tot()
+    f_solid = L.f[:, solid == 1].copy()
+    L.run(25)
+    n1, e1 = tot()
+    assert _rel(n1, n0) < 1e-13 and _rel(e1, e0) < 1e-13, (n1 - n0, e1 - e0)
+    # solid sites are not updated
+    assert np.array_equal(L.f[:, solid == 1], f_solid)
+
+
+def _contact_hit(c, tx, ty, nx, ny):
+    """Is off-lattice point (tx, ty) in the ghost span of contact c?  The span
+    runs along its edge only: a point off the lattice in both axes (a
+    corner) is in no span."""
+    s, e = c["start"], c["start"] + c["width"]
+    if c["edge"] == "bottom":
+        return (ty < 0) & (tx >= s) & (tx < e)
+    if c["edge"] == "top":
+        return (ty >= ny) & (tx >= s) & (tx < e)
+    if c["edge"] == "left":
+        return (tx < 0) & (ty >= s) & (ty < e)
+    return (tx >= nx) & (ty >= s) & (ty < e)
+
+
+@pytest.mark.parametrize("layout", ["sides", "corners"])
+def test_contact_flux_bookkeeping_every_edge(layout):
+    """Global N^0 after one step = N^0 of the post-collision populations that
+    do not land in a contact span + N^0 of the contact equilibria pulled in,
+    with contacts on the left and right edges (and spans that reach the
+    corners)."""
+    st = _st()
+    nx, ny = 36, 30
+    if layout == "sides":
+        contacts = [dict(edge="left", start=6, width=9, n=1.04, T=1.0, vy=0.01),
+                    dict(edge="right", start=14, width=11, n=0.98, T=1.03, vx=-0.01)]
+    else:
+        contacts = [dict(edge="left", start=0, width=8, n=1.03, T=1.0),
+                    dict(edge="bottom", start=0, width=10, n=0.97, T=1.02, vx=0.01),
+                    dict(edge="right", start=ny - 7, width=7, n=1.01, T=0.99),
+                    dict(edge="top", start=nx - 9, width=9, n=1.02, T=1.0, vy=-0.01)]
+    L = oracle.Lattice(st, nx, ny, contacts=contacts, tau=0.8, F=(1e-3, -5e-4))
+    L.init_fields(*_smooth_fields(nx, ny, amp=2e-2))
+    fstar = L.post_collision()
+    y, x = np.mgrid[0:ny, 0:nx]
+    expected = 0.0
+    for i in range(48):
+        dx, dy = st.cx[i], st.cy[i]
+        tx, ty = x + dx, y + dy
+        absorbed = np.zeros_like(x, dtype=bool)
+        for c in contacts:
+            absorbed |= _contact_hit(c, tx, ty, nx, ny)
+        expected += st.p0[i] * fstar[i][~absorbed].sum()
+        sx, sy = x - dx, y - dy
+        for c in contacts:
+            feq = st.feq(c["n"], c["T"], oracle.four_velocity(c.get("vx", 0.0), c.get("vy", 0.0)))
+            expected += st.p0[i] * feq[i] * _contact_hit(c, sx, sy, nx, ny).sum()
+    L.run(1)
+    got = L.totals()["N0"]
+    assert abs(got - expected) < 1e-13 * abs(expected)
+
+
+def _rotate_cw(a):
+    """Scalar field on an nx x ny lattice -> the ny x nx lattice rotated by 90
+    degrees clockwise: the site (x, y) goes to (x', y') = (y, nx - 1 - x)."""
+    ny, nx = a.shape
+    out = np.empty((nx, ny), dtype=a.dtype)
+    y, x = np.mgrid[0:ny, 0:nx]
+    out[nx - 1 - x, y] = a
+    return out
+
+
+def test_rotated_lattice_runs_the_rotated_flow():
+    """The stencil maps to itself under a quarter turn ((cx, cy) -> (cy, -cx)
+    keeps each weight family), so a run rotated by 90 degrees clockwise --
+    bottom contacts onto the left edge, left onto top, top onto right,
+    velocities and drive rotated as vectors -- gives the rotated fields.
+    Ties the left/right/top boundary handling to the bottom one."""
+    st = _st()
+    nx, ny = 34, 26
+    contacts = [dict(edge="bottom", start=3, width=10, n=1.03, T=1.0, vx=0.004, vy=0.002),
+                dict(edge="bottom", start=22, width=9, n=0.98, T=1.01),
+                dict(edge="left", start=0, width=7, n=1.01, T=0.99, vy=-0.003),
+                dict(edge="top", start=20, width=14, n=1.0, T=1.02)]
+    F = (2e-4, -1e-4)
+    n, T, vx, vy = _smooth_fields(nx, ny, amp=2e-2, seed=11)
+    A = oracle.Lattice(st, nx, ny, contacts=contacts, tau=0.9, F=F)
+    A.init_fields(n, T, vx, vy)
+    A.run(12)
+    fa = A.fields()
+    # clockwise quarter turn: a vector (ax, ay) becomes (ay, -ax); edges map
+    # bottom -> left (position along the edge: x -> y' = nx - 1 - x),
+    # left -> top (y -> x' = y), top -> right, right -> bottom
+    rot = []
+    for c in contacts:
+        s, w_ = c["start"], c["width"]
+        if c["edge"] == "bottom":
+            e, s2 = "left", nx - s - w_
+        elif c["edge"] == "top":
+            e, s2 = "right", nx - s - w_
+        elif c["edge"] == "left":
+            e, s2 = "top", s
+        else:
+            e, s2 = "bottom", s
+        rot.append(dict(c, edge=e, start=s2, vx=c.get("vy", 0.0), vy=-c.get("vx", 0.0)))
+    B = oracle.Lattice(st, ny, nx, contacts=rot, tau=0.9, F=(F[1], -F[0]))
+    B.init_fields(_rotate_cw(n), _rotate_cw(T), _rotate_cw(vy), _rotate_cw(-vx))
+    B.run(12)
+    fb = B.fields()
+    assert np.abs(fb["n"] - _rotate_cw(fa["n"])).max() < 1e-13
+    umax = np.hypot(fa["vx"], fa["vy"]).max()
+    assert np.abs(fb["vx"] - _rotate_cw(fa["vy"])).max() < 1e-12 * umax
+    assert np.abs(fb["vy"] - _rotate_cw(-fa["vx"])).max() < 1e-12 * umax
+    # the same run with the sides swapped wrongly (left contact reflected onto
+    # the bottom instead) does not match: the test sees the edge mapping
+    bad = [dict(r, edge="bottom") if r["edge"] == "top" else r for r in rot]
+    C = oracle.Lattice(st, ny, nx, contacts=bad, tau=0.9, F=(F[1], -F[0]))
+    C.init_fields(_rotate_cw(n), _rotate_cw(T), _rotate_cw(vy), _rotate_cw(-vx))
+    C.run(12)
+    assert np.abs(C.fields()["n"] - _rotate_cw(fa["n"])).max() > 1e-8
+
+
+def test_corner_sources_bounce_back_and_spans_pull_equilibria():
+    """Streaming alone on arbitrary post-collision values: at a site next to a
+    corner whose two edges both carry contact spans, a population whose
+    source lies off the lattice in both axes comes back reversed from the
+    site itself (R12: corners are walls), one whose source lies in a span
+    takes that contact's equilibrium, and the rest are pulled."""
+    st = _st()
+    nx, ny = 20, 18
+    contacts = [dict(edge="bottom", start=0, width=12, n=1.05, T=1.0),
+                dict(edge="left", start=0, width=12, n=0.95, T=1.02, vx=0.01)]
+    L = oracle.Lattice(st, nx, ny, contacts=contacts)
+    rng = np.random.default_rng(4)
+    fstar = rng.uniform(0.5, 1.5, size=(48, ny, nx))
+    fnew = L.stream(fstar)
+    feq_b = st.feq(1.05, 1.0, oracle.four_velocity(0.0, 0.0))
+    feq_l = st.feq(0.95, 1.02, oracle.four_velocity(0.01, 0.0))
+    kinds = {"corner": 0, "bottom": 0, "left": 0, "pull": 0}
+    for (x, y) in [(0, 0), (1, 2), (3, 3), (4, 1), (2, 4)]:
+        for i in range(48):
+            sx, sy = x - st.cx[i], y - st.cy[i]
+            got = fnew[i, y, x]
+            if sx < 0 and sy < 0:
+                assert got == fstar[st.opp[i], y, x], (x, y, i)
+                kinds["corner"] += 1
+            elif sy < 0:
+                assert got == feq_b[i], (x, y, i)
+                kinds["bottom"] += 1
+            elif sx < 0:
+                assert got == feq_l[i], (x, y, i)
+                kinds["left"] += 1
+            else:
+                assert got == fstar[i, sy, sx], (x, y, i)
+                kinds["pull"] += 1
+    assert min(kinds.values()) > 0, kinds
+
+
+def test_long_double_build_solves_the_same_problem():
+    """The oracle built with long double arithmetic (the reference that
+    measures the float64 build's rounding floor) runs the same discrete
+    problem on the same float64 constants: on a run with walls, contacts and
+    a drive its fields agree with the float64 build to round-off, and differ
+    from it (it is a different evaluation)."""
+    sd = oracle.stencil()
+    sl = oracle.stencil(long_double=True)
+    assert sl.real == np.longdouble and oracle.lib(True).orc_real_bytes() == 16
+    nx, ny = 30, 22
+    contacts = [dict(edge="bottom", start=4, width=8, n=1.03, T=1.0), dict(edge="right", start=5, width=9, n=0.98)]
+    out = []
+    for st in (sd, sl):
+        L = oracle.Lattice(st, nx, ny, contacts=contacts, tau=0.8, F=(1e-4, 2e-5))
+        L.init_fields(*_smooth_fields(nx, ny, amp=2e-2))
+        L.run(20)
+        out.append(L.fields())
+    umax = float(np.hypot(out[1]["vx"], out[1]["vy"]).max())
+    assert float(np.abs(out[0]["n"] - out[1]["n"]).max()) < 1e-14
+    du = float(np.hypot(out[0]["vx"] - out[1]["vx"], out[0]["vy"] - out[1]["vy"]).max())
+    assert 0.0 < du < 1e-13 * umax
