@@ -238,10 +238,30 @@ class Lattice:
     def init_uniform(self, n=1.0, T=1.0, vx=0.0, vy=0.0):
         check(lib().rlbm_init_uniform(self._h, float(n), float(T), float(vx), float(vy)))
 
+    def _device_field(self, a, name):
+        """A caller-owned field on the device: a contiguous float64 CUDA tensor
+        of nx * ny elements (checked here; the library reads or writes exactly
+        that many)."""
+        import torch
+
+        if not (isinstance(a, torch.Tensor) and a.is_cuda and a.dtype == torch.float64 and a.is_contiguous()
+                and a.numel() == self.nx * self.ny):
+            raise ValueError(f"{name}: need a contiguous float64 CUDA tensor of {self.nx} x {self.ny} elements, got "
+                             f"{getattr(a, 'dtype', type(a))} {tuple(getattr(a, 'shape', ()))} "
+                             f"on {getattr(a, 'device', '?')}")
+        return a
+
     def init_fields(self, n, T, vx, vy):
-        if all(_is_torch(a) for a in (n, T, vx, vy)):
-            ptrs = [a.contiguous().data_ptr() for a in (n, T, vx, vy)]
-            check(lib().rlbm_init_fields(self._h, *ptrs, 1))
+        if any(_is_torch(a) for a in (n, T, vx, vy)):
+            import torch
+
+            fields = [self._device_field(a, k) for a, k in zip((n, T, vx, vy), ("n", "T", "vx", "vy"))]
+            # the init kernel runs on the lattice's stream: order it after the
+            # work that produced the fields, and let it finish before the
+            # caller may free them
+            torch.cuda.current_stream(fields[0].device).synchronize()
+            check(lib().rlbm_init_fields(self._h, *[a.data_ptr() for a in fields], 1))
+            check(lib().rlbm_synchronize(self._h))
             return
         shape = (self.ny, self.nx)
         arrs = [np.ascontiguousarray(np.broadcast_to(_f64(a), shape)) for a in (n, T, vx, vy)]
@@ -271,9 +291,13 @@ class Lattice:
         return out
 
     def read_fields_device(self, n, vx, vy, eps):
-        """Copy the fields into caller-owned device buffers (torch tensors or None)."""
-        ptrs = [None if a is None else a.data_ptr() for a in (n, vx, vy, eps)]
-        check(lib().rlbm_read_fields(self._h, *ptrs, 1))
+        """Copy the fields into caller-owned device buffers (contiguous float64
+        CUDA tensors of nx * ny elements, or None); returns once the copies
+        are done."""
+        outs = [None if a is None else self._device_field(a, k) for a, k in zip((n, vx, vy, eps),
+                                                                                 ("n", "vx", "vy", "eps"))]
+        check(lib().rlbm_read_fields(self._h, *[None if a is None else a.data_ptr() for a in outs], 1))
+        check(lib().rlbm_synchronize(self._h))
 
     def residual(self) -> float:
         r = ctypes.c_double()
