@@ -190,6 +190,21 @@ rlbm_status rlbm_read_fields(rlbm_lattice *lat, double *n, double *vx, double *v
  * non-finite field, n <= 0 or |u| >= 1 (r is still written).  Synchronises. */
 rlbm_status rlbm_residual(rlbm_lattice *lat, double *r);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): rlbm_residual without any
+ * allocation.  Same result as rlbm_residual, bit for bit (the per-block
+ * partial sums are added in the same order), and the same health check
+ * (RLBM_EUNSTABLE).  Its kernels keep their partial sums in a file-scope
+ * device array of the library (3 x 1024 + 3 doubles, 24.6 KB per device,
+ * held until the process ends) instead of the lattice's buffer; every
+ * lattice qualifies (its kernel covers any size with at most 1024 blocks),
+ * and a larger partial-sum count would give RLBM_EINVAL.  The array is
+ * shared by every call on one device: calls that overlap on one device
+ * (several threads, or lattices on several streams) race and must be
+ * serialised by the caller.  The lattice's device must be current
+ * (RLBM_ESTATE otherwise).  Synchronises the lattice's stream. */
+rlbm_status rlbm_residual_noalloc(rlbm_lattice *lat, double *r);
+
 /* Step until the residual over check_every steps falls below tol or
  * max_steps have been taken; writes the steps taken and the last residual.
  * Returns RLBM_EUNSTABLE from the health check. */

@@ -81,6 +81,7 @@ SIGNATURES = {
     "rlbm_get_time": ([_vp, ctypes.POINTER(_i64)], None),
     "rlbm_read_fields": ([_vp, _vp, _vp, _vp, _vp, ctypes.c_int], None),
     "rlbm_residual": ([_vp, _dp], None),
+    "rlbm_residual_noalloc": ([_vp, _dp], None),
     "rlbm_step_until": ([_vp, _i64, _i64, ctypes.c_double, ctypes.POINTER(_i64), _dp], None),
     "rlbm_read_populations": ([_vp, _vp, ctypes.c_int], None),
     "rlbm_state_bytes": ([_vp, ctypes.POINTER(ctypes.c_size_t)], None),
@@ -302,6 +303,12 @@ class Lattice:
     def residual(self) -> float:
         r = ctypes.c_double()
         check(lib().rlbm_residual(self._h, ctypes.byref(r)))
+        return r.value
+
+    def residual_noalloc(self) -> float:
+        """rlbm_residual_noalloc: the same residual, with no allocation."""
+        r = ctypes.c_double()
+        check(lib().rlbm_residual_noalloc(self._h, ctypes.byref(r)))
         return r.value
 
     def read_populations(self) -> np.ndarray:

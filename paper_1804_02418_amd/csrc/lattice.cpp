@@ -108,6 +108,7 @@ void host_feq(const Quadrature &q, double n, double T, double vx, double vy, dou
 
 struct rlbm_lattice {
     int nx = 0, ny = 0;
+    int device = 0;  // the HIP device current at rlbm_create
     rlbm_storage storage = RLBM_F64;
     hipStream_t stream = nullptr;
     Consts C{};
@@ -439,6 +440,10 @@ rlbm_status rlbm_create(int nx, int ny, rlbm_storage storage, void *hip_stream, 
     L->ny = ny;
     L->storage = storage;
     L->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&L->device) != hipSuccess) {
+        delete L;
+        return fail(RLBM_EDEVICE, "rlbm_create: no current HIP device");
+    }
     L->scale = storage == RLBM_F16DEV ? 1.0 / 4096.0 : 1.0;
     L->shape = default_shape(nx);
     // populations that outgrow the 256 MB Infinity Cache are streamed
@@ -744,6 +749,30 @@ rlbm_status rlbm_residual(rlbm_lattice *L, double *r)
     *r = vv > 0 ? std::sqrt(dv) / (K * std::sqrt(vv)) : 0.0;
     if (bad > 0 || !std::isfinite(*r))
         return fail(RLBM_EUNSTABLE, "health check: %.0f unhealthy sites at step %lld", bad, (long long)L->t);
+    return RLBM_OK;
+}
+
+rlbm_status rlbm_residual_noalloc(rlbm_lattice *L, double *r)
+{
+    CHECK_L(L);
+    if (!r) return fail(RLBM_EINVAL, "rlbm_residual_noalloc: NULL");
+    if (!L->fields_valid) return fail(RLBM_ESTATE, "rlbm_residual_noalloc: no fields");
+    if (L->part_blocks > kNoAllocResidualBlocks)
+        return fail(RLBM_EINVAL, "rlbm_residual_noalloc: %d partial sums exceed the scratch of %d", L->part_blocks,
+                    kNoAllocResidualBlocks);
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != L->device)
+        return fail(RLBM_ESTATE, "rlbm_residual_noalloc: the lattice lives on device %d but device %d is current",
+                    L->device, dev);
+    const size_t P = (size_t)L->plane();
+    double tot[3];
+    HIP_TRY(launch_residual_noalloc((int)P, L->mask, L->fld, L->fld + P, L->fld + 2 * P, L->prev, L->prev + P,
+                                    L->part_blocks, tot, L->stream));
+    const double K = L->last_K > 0 ? (double)L->last_K : 1.0;
+    *r = tot[1] > 0 ? std::sqrt(tot[0]) / (K * std::sqrt(tot[1])) : 0.0;
+    if (tot[2] > 0 || !std::isfinite(*r))
+        return fail(RLBM_EUNSTABLE, "health check: %.0f unhealthy sites at step %lld", tot[2], (long long)L->t);
     return RLBM_OK;
 }
 

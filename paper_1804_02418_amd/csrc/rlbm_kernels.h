@@ -198,4 +198,14 @@ hipError_t launch_residual(int nsites, const unsigned char *mask, const double *
                            const double *vy, const double *pvx, const double *pvy, double *part, int nblocks,
                            hipStream_t s);
 
+// The same residual sums without any buffer from the caller or the library:
+// the partial sums (nblocks <= kNoAllocResidualBlocks) and their totals go
+// through a file-scope device array of the current device; totals[3] (host)
+// receives sum |u - u_prev|^2, sum |u|^2 and the unhealthy count, added in
+// the order launch_residual's caller adds them.  Synchronises the stream.
+constexpr int kNoAllocResidualBlocks = 1024;
+hipError_t launch_residual_noalloc(int nsites, const unsigned char *mask, const double *n, const double *vx,
+                                   const double *vy, const double *pvx, const double *pvy, int nblocks,
+                                   double totals[3], hipStream_t s);
+
 }  // namespace rlbm

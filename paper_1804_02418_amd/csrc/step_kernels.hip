@@ -1,6 +1,8 @@
 // Dispatch of the step kernels by storage (each storage's kernels live in a
 // translation unit of their own: step_f64.hip, step_f32.hip, step_f16.hip)
 // and the storage-independent residual kernel.
+#include <mutex>
+
 #include "rlbm_kernels.h"
 
 namespace rlbm {
@@ -130,6 +132,79 @@ hipError_t launch_residual(int nsites, const unsigned char *mask, const double *
 {
     hipLaunchKernelGGL(residual_kernel, dim3(nblocks), dim3(256), 0, s, nsites, mask, n, vx, vy, pvx, pvy, part);
     return hipGetLastError();
+}
+
+// ---- residual without allocation ----
+//
+// The per-block partial sums of residual_kernel and their three totals live
+// in this file-scope array instead of a buffer the library allocates: one
+// copy per device, held until the process ends and shared by every call on
+// that device (calls that overlap on one device race).  Each call overwrites
+// the partial sums it reads and the totals, so nothing needs clearing.
+static __device__ __align__(256) double scratch[3 * kNoAllocResidualBlocks + 3];
+
+namespace {
+
+// The device address of `scratch`, per device (the array's name in host code
+// only stands in for it), looked up on the first call on each device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+hipError_t scratch_of_current_device(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch[dev];
+    return hipSuccess;
+}
+
+// One thread adds the partial sums in block order, as the host loop of the
+// allocating residual does, so both give the same totals bit for bit.
+__global__ __launch_bounds__(64) void residual_total_kernel(const double *__restrict__ part, int nblocks,
+                                                            double *__restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double dv = 0.0, vv = 0.0, bad = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        dv += part[3 * b];
+        vv += part[3 * b + 1];
+        bad += part[3 * b + 2];
+    }
+    out[0] = dv;
+    out[1] = vv;
+    out[2] = bad;
+}
+
+}  // namespace
+
+hipError_t launch_residual_noalloc(int nsites, const unsigned char *mask, const double *n, const double *vx,
+                                   const double *vy, const double *pvx, const double *pvy, int nblocks,
+                                   double totals[3], hipStream_t s)
+{
+    if (nblocks < 1 || nblocks > kNoAllocResidualBlocks || !totals) return hipErrorInvalidValue;
+    double *ptr = nullptr;
+    hipError_t e = scratch_of_current_device(&ptr);
+    if (e != hipSuccess) return e;
+    double *tot = ptr + 3 * kNoAllocResidualBlocks;
+    hipLaunchKernelGGL(residual_kernel, dim3(nblocks), dim3(256), 0, s, nsites, mask, n, vx, vy, pvx, pvy, ptr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(residual_total_kernel, dim3(1), dim3(64), 0, s, ptr, nblocks, tot);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(totals, tot, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
 }
 
 }  // namespace rlbm
