@@ -16,6 +16,10 @@ arranges batches and bookkeeping.
 * Warm start (``decode``): n = 1 + F p0, v = F (p1, p2) / (tau - 1/2),
   T = 1; the prediction is rejected (cold start instead) if any value is
   non-finite, n <= 0 or |v| >= 1.
+* Fallback during the solve (``solve_warm``): the plain solver judges every
+  warm start.  A warm-started sample whose residual rises above ``growth``
+  times the smallest residual it has reached, or that fails the health
+  check, is restarted from the cold start (the steps it spent count).
 """
 from __future__ import annotations
 
@@ -86,6 +90,81 @@ def solve_batch(samples, max_steps, check_every=100, tol=1e-8, storage="f64", in
     bt.close()
     torch.cuda.synchronize()
     return fields, steps, r, time.perf_counter() - t0
+
+
+def solve_warm(samples, inits, max_steps, check_every=100, tol=1e-8, growth=10.0, storage="f64"):
+    """Batched solve from warm starts with the plain solver as the fallback.
+
+    inits: per sample (n, vx, vy) or None (a rejected prediction: cold
+    start).  See warm_loop for the schedule and the fallback rule.  Returns
+    (fields list, steps array (counting steps spent before a restart),
+    residuals array, seconds, restart step per sample (-1: none))."""
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt = B.Batch(samples, storage)
+    for L, st in zip(bt.lattices, inits):
+        if st is not None:
+            nn, vx, vy = st
+            L.init_fields(nn, np.ones_like(nn), vx, vy)
+    warm = np.array([st is not None for st in inits], dtype=bool)
+    steps, res, restart = warm_loop(bt, samples, warm, max_steps, check_every, tol, growth)
+    fields = [L.read_fields() for L in bt.lattices]
+    bt.close()
+    torch.cuda.synchronize()
+    return fields, steps, res, time.perf_counter() - t0, restart
+
+
+def warm_loop(bt, samples, warm, max_steps, check_every, tol, growth):
+    """The checked solve of solve_warm on an initialised batch bt.
+
+    Every check_every steps the batch residuals are read; a sample stops (is
+    frozen) once its residual over a full interval is below tol.  A
+    warm-started sample is restarted cold -- the uniform equilibrium of its
+    description -- when its residual exceeds growth times the smallest it
+    has reached, or when it fails the health check; it is restarted at most
+    once.  A sample failing the health check from a cold start raises
+    Unstable.  Returns (steps, residuals, restart step or -1) per sample."""
+    n = len(samples)
+    steps = np.zeros(n, dtype=np.int64)
+    res = np.full(n, np.inf)
+    best = np.full(n, np.inf)
+    restart = np.full(n, -1, dtype=np.int64)
+    active = np.ones(n, dtype=bool)
+    done = 0
+    while active.any() and done < max_steps:
+        k = min(check_every, max_steps - done)
+        bt.set_active(active.astype(np.uint8))
+        bt.step(k)
+        done += k
+        sick = np.zeros(n, dtype=bool)
+        try:
+            r = bt.residual()
+        except B.Unstable:
+            # which samples failed: each active lattice's own health check
+            r = np.array(res)
+            for s in np.flatnonzero(active):
+                try:
+                    r[s] = bt.lattices[s].residual()
+                except B.Unstable:
+                    r[s], sick[s] = np.inf, True
+        for s in np.flatnonzero(active):
+            steps[s] += k
+            res[s] = r[s]
+            if warm[s] and restart[s] < 0 and (sick[s] or r[s] > growth * best[s]):
+                i = samples[s].get("init", {})
+                bt.lattices[s].init_uniform(i.get("n", 1.0), i.get("T", 1.0), i.get("vx", 0.0), i.get("vy", 0.0))
+                restart[s] = steps[s]
+                res[s] = best[s] = np.inf
+                continue
+            if sick[s]:
+                raise B.Unstable(B.EUNSTABLE, f"sample {s} failed the health check from a cold start")
+            best[s] = min(best[s], r[s])
+            if k == check_every and r[s] < tol:
+                active[s] = False
+    bt.set_active(np.ones(n, dtype=np.uint8))
+    return steps, res, restart
 
 
 def generate(count, size=256, seed_offset=0, max_steps=300_000, tol=1e-8, chunk=256, log=print):

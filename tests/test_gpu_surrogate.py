@@ -303,3 +303,54 @@ def test_trained_surrogate_warm_start_saves_steps():
     print("warm steps", steps_w, "cold steps", steps_c, flush=True)
     assert (r_w < 1e-8).all() and (r_c < 1e-8).all()
     assert np.median(steps_w) < np.median(steps_c)
+
+
+def test_rejected_predictions_start_cold():
+    """Predictions with a non-finite value, a density n <= 0 or a speed
+    |v| >= 1 are rejected and those samples run from the cold start: the
+    checked warm solve then gives, bit for bit, the plain solver's run."""
+    from paper_1804_02418_amd import surrogate as SU
+    from paper_1804_02418_amd import workloads
+
+    held = workloads.batch_samples(3, fixed_size=(256, 128))
+    preds = np.zeros((3, 128, 256, 3), dtype=np.float32)
+    preds[0, 40, 100, 1] = np.nan
+    preds[1, ..., 0] = -2.0 / SU.drive(held[1])                              # n = -1
+    preds[2, 7, 9, 1] = 1.5 * (held[2]["tau"] - 0.5) / SU.drive(held[2])   # |v| = 1.5
+    inits = SU.warm_start_inits(held, preds)
+    assert inits == [None, None, None]
+    fw, steps_w, r_w, _, restart = SU.solve_warm(held, inits, 1500, tol=1e-30)
+    fc, steps_c, r_c, _ = SU.solve_batch(held, 1500, tol=1e-30)
+    assert list(restart) == [-1, -1, -1]
+    assert list(steps_w) == list(steps_c) == [1500] * 3
+    for a, b in zip(fw, fc):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(r_w, r_c)
+
+
+def test_failing_warm_start_restarts_cold():
+    """A prediction that passes the checks but throws the lattice off (a
+    checkerboard of +-0.9 c) fails the health check within the first
+    interval; that sample restarts from the cold start, and from there its
+    run is the plain solver's run of the remaining steps, bit for bit.  The
+    well-predicted sample beside it (the uniform state, an exact warm start
+    of nothing) is untouched."""
+    from paper_1804_02418_amd import surrogate as SU
+    from paper_1804_02418_amd import workloads
+
+    held = workloads.batch_samples(2, fixed_size=(256, 128))
+    ny, nx = 128, 256
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    wild = (0.9 * np.where((xx + yy) % 2 == 0, 1.0, -1.0), np.zeros((ny, nx)))
+    inits = [(np.ones((ny, nx)), *wild), (np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)))]
+    fw, steps_w, _, _, restart = SU.solve_warm(held, inits, 1200, tol=1e-30)
+    print("restart steps", restart, "steps", steps_w, flush=True)
+    assert restart[0] == 100 and restart[1] == -1
+    assert list(steps_w) == [1200, 1200]
+    fc, _, _, _ = SU.solve_batch([held[0]], 1200 - 100, tol=1e-30)
+    for k in fc[0]:
+        assert np.array_equal(fw[0][k], fc[0][k]), k
+    fu, _, _, _ = SU.solve_batch([held[1]], 1200, tol=1e-30)
+    for k in fu[0]:
+        assert np.array_equal(fw[1][k], fu[0][k]), k
