@@ -1,20 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark of the fused relativistic LB step on one MI355X.
 
-Workload (default): the 1024 x 512 graphene sample -- bounce-back walls on
-every edge, source and drain contacts 32 wide on the bottom edge with
-centres 256 apart, uniform drive F = 1e-5 along +x, tau = 0.8, FP32
+Workload (default): the 4096 x 2048 graphene sample -- bounce-back walls on
+every edge, source and drain contacts 128 wide on the bottom edge with
+centres 1024 apart, uniform drive F = 1e-5 along +x, tau = 0.8, FP32
 populations, uniform equilibrium start -- stepped K times after W warm-up
-steps.  One step = one pass of the whole per-site update (pull with
-boundary rules, moments, Landau frame, equilibrium, force, relaxation,
-store) over every site.
+steps.  Its two population arrays (3.2 GB) are far larger than the 256 MB
+Infinity Cache, so the step streams from HBM.  One step = one pass of the
+whole per-site update (pull with boundary rules, moments, Landau frame,
+equilibrium, force, relaxation, store) over every site.
 
 Prints one JSON line: MLUPS (million lattice-site updates per second), the
 HBM roofline of the step kernel (algorithmic bytes per launch over the
 average launch time measured with HIP events on the kernel's stream), the
-aggregate throughput of the 256-sample uneven batch on the batched kernel,
-the surrogate's warm- vs cold-start time to a steady state, and the FP64
-CPU oracle timed on a bounded sample on this host.
+same over a longer sustained run, the other storages and the 1024 x 512
+sample (whose FP32 and FP16 arrays stay in the Infinity Cache), the
+precision of every storage against the FP64 oracle (stored oracle fields
+after 200 steps, 8 x 8 block means) and against the FP64 path after 20 000
+steps, the aggregate throughput of the 256-sample uneven batch, the
+surrogate's warm- vs cold-start time to a steady state, and the FP64 CPU
+oracle timed on a bounded sample on this host.
 """
 from __future__ import annotations
 
@@ -24,6 +29,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
@@ -96,9 +103,21 @@ def run_gpu(w, storage, steps, warmup, autotune=True):
     return ms / 1e3, ms / max(steps, 1), r
 
 
-def cpu_baseline(w, steps: int):
-    import numpy as np
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def cpu_baseline(w, steps: int):
+    """The FP64 oracle on this host's cores: `steps` steps of the workload
+    from its uniform start on every thread, then one more on one thread.
+    Returns (record, oracle fields after `steps` steps)."""
     import oracle
 
     st = oracle.stencil()
@@ -112,18 +131,18 @@ def cpu_baseline(w, steps: int):
     O.run(steps)
     dt = time.perf_counter() - t0
     ref = O.fields()
-    # the same oracle on one thread, over a twentieth of the steps
-    s1 = max(1, steps // 20)
     lib.orc_set_threads(1)
     t1 = time.perf_counter()
-    O.run(s1)
+    O.run(1)
     d1 = time.perf_counter() - t1
     lib.orc_set_threads(cores)
-    base = {"value": w["nx"] * w["ny"] * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+    sites = w["nx"] * w["ny"]
+    base = {"value": round(sites * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{w['nx']}x{w['ny']} graphene sample, {steps} steps from the uniform start, FP64, "
-                      f"{dt:.1f} s",
-            "single_thread": {"value": w["nx"] * w["ny"] * s1 / d1 / 1e6, "unit": "MLUPS",
-                              "sample": f"the next {s1} steps, {d1:.1f} s"}}
+                      f"{cores} threads, {dt:.1f} s",
+            "single_thread": {"value": round(sites / d1 / 1e6, 3), "unit": "MLUPS",
+                              "sample": f"the next step on one thread, {d1:.1f} s"}}
     return base, ref
 
 
@@ -147,6 +166,86 @@ def errors_vs_oracle(w, steps: int, ref):
         out[st] = {"err_n": float(np.max(np.abs(g["n"][fluid] - rn) / np.abs(rn))),
                    "err_u": float(du.max() / ru.max())}
     out["max_u"] = float(ru.max())
+    return out
+
+
+GOLDEN = os.path.join(HERE, "tests", "golden")
+
+
+def _field_errors(g, ref, sel=None):
+    """err_n = max |n - n_ref| / |n_ref|; err_u = max |u - u_ref| / max |u_ref|."""
+    sel = np.ones_like(ref["n"], dtype=bool) if sel is None else sel
+    du = np.hypot(g["vx"] - ref["vx"], g["vy"] - ref["vy"])[sel]
+    return {"err_n": float(np.max(np.abs(g["n"][sel] - ref["n"][sel]) / np.abs(ref["n"][sel]))),
+            "err_u": float(du.max() / np.hypot(ref["vx"], ref["vy"])[sel].max())}
+
+
+def precision_vs_oracle(w, steps: int = 200, block: int = 8):
+    """Every storage after `steps` steps from the uniform start against the
+    FP64 oracle's fields of the same run (stored by
+    tests/golden/make_graphene_goldens.py, which calls only the oracle): at
+    the stored sites, and on the block-mean downsample (8 x 8 blocks: 512 x
+    256 at 4096 x 2048).  None if the file is missing."""
+    import torch
+
+    path = os.path.join(GOLDEN, f"graphene_{w['nx']}x{w['ny']}_t{steps}.npz")
+    if not os.path.exists(path):
+        return None
+    gd = np.load(path)
+    meta = json.loads(str(gd["meta"]))
+    sites = gd["sites"]
+    ref = {k: gd[k] for k in ("n", "vx", "vy")}
+    umax = meta["umax"]
+    nx, ny = w["nx"], w["ny"]
+
+    def down(a):
+        return a.reshape(ny // block, block, nx // block, block).mean(axis=(1, 3))
+
+    dref = {"n": 1.0 + gd["down_n1"].astype(np.float64), "vx": gd["down_vx"].astype(np.float64),
+            "vy": gd["down_vy"].astype(np.float64)} if "down_n1" in gd else None
+    out = {"steps": steps, "reference": "FP64 oracle (stored fields)", "stored_sites": int(sites.size),
+           "oracle_float64_vs_long_double": meta.get("floor")}
+    for st in ("f64", "f32", "f16dev"):
+        L = make_lattice(w, st, torch.cuda.current_stream().cuda_stream)
+        L.step(steps)
+        g = L.read_fields()
+        L.close()
+        at = {k: g[k].ravel()[sites] for k in ("n", "vx", "vy")}
+        du = np.hypot(at["vx"] - ref["vx"], at["vy"] - ref["vy"])
+        rec = {"sites": {"err_n": float(np.max(np.abs(at["n"] - ref["n"]) / np.abs(ref["n"]))),
+                         "err_u": float(du.max() / umax)}}
+        if dref is not None:
+            gdn = {k: down(g[k]) for k in ("n", "vx", "vy")}
+            rec["downsample"] = _field_errors(gdn, dref)
+        out[st] = rec
+    return out
+
+
+def precision_long_run(w, steps: int = 20000, block: int = 8):
+    """FP32 and FP16-deviation storage against the FP64 path after `steps`
+    steps (the FP64 path is tied to the FP64 oracle by the parity tests and
+    the stored-oracle comparison): full fields and 8 x 8 block means."""
+    import torch
+
+    nx, ny = w["nx"], w["ny"]
+
+    def down(a):
+        return a.reshape(ny // block, block, nx // block, block).mean(axis=(1, 3))
+
+    fields = {}
+    for st in ("f64", "f32", "f16dev"):
+        L = make_lattice(w, st, torch.cuda.current_stream().cuda_stream)
+        L.step(steps)
+        fields[st] = L.read_fields()
+        L.close()
+    ref = fields["f64"]
+    dref = {k: down(ref[k]) for k in ("n", "vx", "vy")}
+    out = {"steps": steps, "reference": "FP64 storage on the GPU", "downsample": [ny // block, nx // block],
+           "max_u": float(np.hypot(ref["vx"], ref["vy"]).max())}
+    for st in ("f32", "f16dev"):
+        g = fields[st]
+        out[st] = {"full": _field_errors(g, ref),
+                   "downsample": _field_errors({k: down(g[k]) for k in ("n", "vx", "vy")}, dref)}
     return out
 
 
@@ -184,11 +283,12 @@ def bandwidth_probes():
             g, u = B.bandwidth_probe(pattern, 4, nx, ny, nt, reps)
             rows.append({"pattern": pattern, "nontemporal": nt, "array_bytes": 48 * 4 * nx * ny, "GBs": round(g, 1),
                          "us": round(u, 2)})
-    for elem, nx, ny, reps in ((4, 4096, 2048, 20), (2, 4096, 2048, 20), (8, 4096, 2048, 10), (4, 1024, 512, 200)):
-        for nt in (False, True):
-            g, u = B.bandwidth_probe("pull48", elem, nx, ny, nt, reps)
-            rows.append({"pattern": "pull48", "elem_bytes": elem, "nx": nx, "ny": ny, "nontemporal": nt,
-                         "GBs": round(g, 1), "us": round(u, 2)})
+    for pattern in ("pull48", "pull48_pair"):
+        for elem, nx, ny, reps in ((4, 4096, 2048, 20), (2, 4096, 2048, 20), (8, 4096, 2048, 10), (4, 1024, 512, 200)):
+            for nt in (False, True):
+                g, u = B.bandwidth_probe(pattern, elem, nx, ny, nt, reps)
+                rows.append({"pattern": pattern, "elem_bytes": elem, "nx": nx, "ny": ny, "nontemporal": nt,
+                             "GBs": round(g, 1), "us": round(u, 2)})
     rows.append(dict(pattern="torch device copy", **copy_calibration(1 << 30)))
     return rows
 
@@ -196,66 +296,27 @@ def bandwidth_probes():
 WEIGHTS = os.path.join(HERE, "paper_1804_02418_amd", "data", "unet_graphene256.npz")
 
 
-def precision_report(nx: int = 4096, ny: int = 2048, steps: int = 20000, block: int = 8):
-    """Run the graphene sample in FP64, FP32 and FP16-deviation storage for
-    `steps` steps and report the max-relative errors of FP32 and FP16 against
-    FP64 on the block-mean downsample (8 x 8 blocks: 512 x 256 at 4096 x
-    2048), and on the full fields.  The FP64 path is the reference: it is held
-    to the FP64 oracle at 1e-12 by the parity tests."""
-    import numpy as np
-    import torch
-
+def main_precision(argv):
+    """--precision-report: the long-run precision leg alone (any size, steps)."""
     from paper_1804_02418_amd import workloads
 
-    w = workloads.graphene_sample(nx, ny)
-
-    def down(a):
-        return a.reshape(ny // block, block, nx // block, block).mean(axis=(1, 3))
-
-    fields, times = {}, {}
-    for st in ("f64", "f32", "f16dev"):
-        stream = torch.cuda.current_stream()
-        L = make_lattice(w, st, stream.cuda_stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        L.step(steps)
-        f = L.read_fields()
-        times[st] = time.perf_counter() - t0
-        fields[st] = f
-        L.close()
-    ref = fields["f64"]
-    out = {"workload": w["name"], "steps": steps, "downsample": [ny // block, nx // block],
-           "seconds": {k: round(v, 2) for k, v in times.items()}}
-    for st in ("f32", "f16dev"):
-        g = fields[st]
-        rep = {}
-        for tag, fn in (("downsampled", down), ("full", lambda a: a)):
-            rn, gn = fn(ref["n"]), fn(g["n"])
-            ru = np.hypot(fn(ref["vx"]), fn(ref["vy"]))
-            du = np.hypot(fn(g["vx"]) - fn(ref["vx"]), fn(g["vy"]) - fn(ref["vy"]))
-            rep[tag] = {"err_n": float(np.max(np.abs(gn - rn) / np.abs(rn))),
-                        "err_u": float(du.max() / ru.max()), "max_u": float(ru.max())}
-        out[st] = rep
-    return out
-
-
-def main_precision(argv):
     ap = argparse.ArgumentParser()
     ap.add_argument("--nx", type=int, default=4096)
     ap.add_argument("--ny", type=int, default=2048)
     ap.add_argument("--steps", type=int, default=20000)
     a = ap.parse_args(argv)
-    print(json.dumps(precision_report(a.nx, a.ny, a.steps)), flush=True)
+    w = workloads.graphene_sample(a.nx, a.ny)
+    print(json.dumps({"precision_long_run": precision_long_run(w, a.steps)}), flush=True)
     return 0
 
 
-def warm_vs_cold(path: str, count: int = 16, first_index: int = 6000, tol: float = 1e-8,
+def warm_vs_cold(path: str, count: int = 64, first_index: int = 6000, tol: float = 1e-8,
                  max_steps: int = 400_000):
     """Time to a 1e-8 residual of `count` held-out 256 x 256 samples (seeds
     disjoint from the training set), started cold (uniform equilibrium) and
-    warm (the trained surrogate's prediction), each as one batched FP64 run.
-    Warm wall time includes the network's inference."""
-    import numpy as np
+    warm (the trained surrogate's prediction, with the plain solver as the
+    fallback), each as one batched FP64 run.  Warm wall time includes the
+    network's inference."""
     import torch
 
     from paper_1804_02418_amd import _binding as B
@@ -274,16 +335,26 @@ def warm_vs_cold(path: str, count: int = 16, first_index: int = 6000, tol: float
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
     inits = S.warm_start_inits(held, preds)
-    _, steps_w, r_w, t_w = S.solve_batch(held, max_steps, tol=tol, init=inits)
-    _, steps_c, r_c, t_c = S.solve_batch(held, max_steps, tol=tol)
+    fw, steps_w, r_w, t_w, restart = S.solve_warm(held, inits, max_steps, tol=tol)
+    fc, steps_c, r_c, t_c = S.solve_batch(held, max_steps, tol=tol)
     net.close()
-    return {"samples": count, "size": size, "tol": tol,
+    # prediction error against the converged cold solution, relative RMS of the velocity
+    rel = [float(np.sqrt(np.mean((np.hypot(*(S.decode(w, p)[1:]) ) - np.hypot(c["vx"], c["vy"])) ** 2)) /
+                 np.sqrt(np.mean(np.hypot(c["vx"], c["vy"]) ** 2)))
+           for w, p, c in zip(held, preds, fc) if S.decode(w, p) is not None]
+    ratio = steps_w / np.maximum(steps_c, 1)
+    return {"samples": count, "size": size, "tol": tol, "first_seed": first_index,
             "cold": {"steps_median": float(np.median(steps_c)), "steps_mean": float(np.mean(steps_c)),
                      "seconds": round(t_c, 3), "converged": int((r_c < tol).sum())},
             "warm": {"steps_median": float(np.median(steps_w)), "steps_mean": float(np.mean(steps_w)),
                      "seconds_incl_inference": round(t_w + t_inf, 3), "inference_seconds": round(t_inf, 4),
                      "converged": int((r_w < tol).sum()),
-                     "fallbacks": sum(1 for i in inits if i is None)},
+                     "rejected_predictions": sum(1 for i in inits if i is None),
+                     "restarted_cold": int((restart >= 0).sum())},
+            "steps_ratio_warm_over_cold": {"median": round(float(np.median(ratio)), 4),
+                                           "p10": round(float(np.percentile(ratio, 10)), 4),
+                                           "p90": round(float(np.percentile(ratio, 90)), 4)},
+            "prediction_rel_rms_velocity_median": round(float(np.median(rel)), 4) if rel else None,
             "speedup_wall": round(t_c / (t_w + t_inf), 3)}
 
 
@@ -396,29 +467,44 @@ def surrogate_throughput(batch: int = 8, size: int = 256, steps: int = 20, warmu
             "forward_frac": round(fwd / (ms_infer / 1e3) / 1e12 / PEAK_BF16_TFLOPS, 4)}
 
 
+def cache_resident(w, storage) -> bool:
+    """Both population arrays fit the 256 MB Infinity Cache (the step then
+    need not stream from HBM)."""
+    return 2 * 48 * BYTES_PER_POP[storage] * w["nx"] * w["ny"] <= 256 * 2 ** 20
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16dev"])
-    ap.add_argument("--nx", type=int, default=1024)
-    ap.add_argument("--ny", type=int, default=512)
-    ap.add_argument("--cpu-steps", type=int, default=200, help="oracle steps for the CPU baseline (0 = skip)")
+    ap.add_argument("--nx", type=int, default=4096)
+    ap.add_argument("--ny", type=int, default=2048)
+    ap.add_argument("--cpu-steps", type=int, default=16, help="oracle steps for the CPU baseline (0 = skip)")
+    ap.add_argument("--sustained-steps", type=int, default=1000,
+                    help="steps of the separately timed sustained run (0 = skip)")
+    ap.add_argument("--long-run-steps", type=int, default=20000,
+                    help="steps of the FP32 / FP16 vs FP64 precision leg (0 = skip)")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the surrogate warm- vs cold-start timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-sample batched-kernel throughput")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate network throughput")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision legs")
     ap.add_argument("--surrogate-only", action="store_true", help="only time the surrogate network")
     ap.add_argument("--batch-only", action="store_true", help="only time the 256-sample batch")
     ap.add_argument("--bandwidth-probes", action="store_true",
                     help="only measure read, copy and 48-plane pull bandwidth (the practical ceilings)")
     ap.add_argument("--batch-steps", type=int, default=100, help="timed steps per batch configuration")
     ap.add_argument("--no-variants", action="store_true",
-                    help="skip the other storages at this size and the three storages at 4096x2048")
+                    help="skip the other storages at this size and the 1024 x 512 sample")
     ap.add_argument("--copy-bytes", type=int, default=0, help="only run the copy-bandwidth calibration")
     ap.add_argument("--no-autotune", action="store_true", help="time the default launch shape")
     args = ap.parse_args(argv)
 
+    if args.gpus != 1:
+        print(json.dumps({"error": "this library runs on one GPU only; y-slab sharding across GPUs is "
+                                   "designed but not implemented", "n_gpus": args.gpus}), flush=True)
+        return 2
     if args.copy_bytes:
         print(json.dumps(copy_calibration(args.copy_bytes)), flush=True)
         return 0
@@ -433,19 +519,14 @@ def main(argv=None):
         print(json.dumps({"batch_256": batch_throughput(steps=args.batch_steps)}), flush=True)
         return 0
 
-    if args.gpus != 1:
-        print(json.dumps({"error": "this library runs on one GPU only; y-slab sharding across GPUs is "
-                                   "designed but not implemented", "n_gpus": args.gpus}))
-        return 2
-
     from paper_1804_02418_amd import workloads
 
     w = workloads.graphene_sample(args.nx, args.ny, storage=args.storage, steps=args.steps)
     sites = w["nx"] * w["ny"]
+    per_site = 2 * 48 * BYTES_PER_POP[args.storage]
     secs, launch_ms, resid = run_gpu(w, args.storage, args.steps, args.warmup, not args.no_autotune)
     mlups = sites * args.steps / secs / 1e6
-    bytes_per_launch = 2 * 48 * BYTES_PER_POP[args.storage] * sites
-    achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
+    achieved = per_site * sites / (launch_ms / 1e3) / 1e9
     out = {
         "metric": "MLUPS & % HBM roofline; warm-start vs cold time-to-steady at 1e-8 residual",
         "value": round(mlups, 1),
@@ -461,36 +542,51 @@ def main(argv=None):
         "data": "synthetic",
         "config": {"workload": w["name"], "nx": w["nx"], "ny": w["ny"], "storage": args.storage, "tau": w["tau"],
                    "drive": w["F"][0], "contacts": [[c["start"], c["width"]] for c in w["contacts"]],
-                   "parallelism": "single GPU"},
+                   "cache_resident": cache_resident(w, args.storage), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(f"step_{args.storage}_{w['nx']}x{w['ny']}", sites)},
         "residual_last_call": resid,
     }
+    print(f"headline {mlups:.1f} MLUPS, {achieved / PEAK_HBM_GBS:.4f} of HBM peak", file=sys.stderr, flush=True)
+    if args.sustained_steps > 0:
+        s2, l2, _ = run_gpu(w, args.storage, args.sustained_steps, args.warmup, not args.no_autotune)
+        g2 = per_site * sites / (l2 / 1e3) / 1e9
+        out["sustained"] = {"steps": args.sustained_steps, "mlups": round(sites * args.sustained_steps / s2 / 1e6, 1),
+                            "hbm_gbs": round(g2, 1), "frac": round(g2 / PEAK_HBM_GBS, 4)}
     if not args.no_variants:
-        # the same step at the other storages, and the 4096 x 2048 sample (the
-        # populations no longer fit the 256 MB Infinity Cache) at all three
+        # the other storages at this size, and the 1024 x 512 sample in all three
         extra = {}
 
         def variant(wv, st, steps, warmup):
-            s2, l2, _ = run_gpu(wv, st, steps, warmup)
+            s3, l3, _ = run_gpu(wv, st, steps, warmup)
             n = wv["nx"] * wv["ny"]
-            gbs = 2 * 48 * BYTES_PER_POP[st] * n / (l2 / 1e3) / 1e9
-            extra[f"{wv['name']}_{st}"] = {"mlups": round(n * steps / s2 / 1e6, 1), "hbm_gbs": round(gbs, 1),
-                                           "frac": round(gbs / PEAK_HBM_GBS, 4)}
+            gbs = 2 * 48 * BYTES_PER_POP[st] * n / (l3 / 1e3) / 1e9
+            extra[f"{wv['name']}_{st}"] = {"mlups": round(n * steps / s3 / 1e6, 1), "hbm_gbs": round(gbs, 1),
+                                           "frac": round(gbs / PEAK_HBM_GBS, 4),
+                                           "cache_resident": cache_resident(wv, st), "steps": steps}
 
-        for st in ("f64", "f16dev"):
-            variant(w, st, 2000, 100)
-        big = workloads.graphene_sample(4096, 2048)
         for st in ("f64", "f32", "f16dev"):
-            variant(big, st, 200, 20)
+            if st != args.storage:
+                variant(w, st, 500, 50)
+        small = workloads.graphene_sample(1024, 512)
+        for st in ("f64", "f32", "f16dev"):
+            variant(small, st, 4000, 200)
         out["variants"] = extra
+        print("variants done", file=sys.stderr, flush=True)
     if not args.no_batch:
-        out["batch_256"] = batch_throughput(args.storage)
+        out["batch_256"] = batch_throughput(args.storage if args.storage != "f64" else "f32")
+        print("batch done", file=sys.stderr, flush=True)
     if not args.no_surrogate:
         out["surrogate"] = surrogate_throughput()
     if not args.no_warm_start and os.path.exists(WEIGHTS):
         out["time_to_steady"] = warm_vs_cold(WEIGHTS)
+        print("time to steady done", file=sys.stderr, flush=True)
+    if not args.no_precision:
+        out["precision_vs_oracle"] = precision_vs_oracle(w)
+        if args.long_run_steps > 0:
+            out["precision_long_run"] = precision_long_run(w, args.long_run_steps)
+        print("precision done", file=sys.stderr, flush=True)
     if args.cpu_steps > 0:
         out["cpu_baseline"], ref = cpu_baseline(w, args.cpu_steps)
         out["errors_vs_oracle"] = errors_vs_oracle(w, args.cpu_steps, ref)

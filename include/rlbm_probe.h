@@ -16,9 +16,13 @@ extern "C" {
 typedef enum {
     RLBM_PROBE_READ = 0,   /* read the array once (16-byte loads, four per thread in flight) */
     RLBM_PROBE_COPY = 1,   /* copy it into a second array (16-byte loads and stores, four per thread) */
-    RLBM_PROBE_PULL48 = 2  /* the step's pattern: at every site with x, y in [5, n - 5), 48 loads from the
+    RLBM_PROBE_PULL48 = 2, /* the step's pattern: at every site with x, y in [5, n - 5), 48 loads from the
                               planes of the population layout, each shifted by its population's hop, and 48
                               aligned stores, with trivial arithmetic between them */
+    RLBM_PROBE_PULL48_PAIR = 3 /* the same with two adjacent sites (x even, x in [6, nx - 6)) per thread: each
+                                  plane read as one two-element load from the hop-shifted address (aligned to
+                                  one element only for odd hops) and written as one aligned two-element store;
+                                  nx must be even */
 } rlbm_probe_pattern;
 
 /* Time `pattern` on arrays the size of one population array of an nx x ny
@@ -30,7 +34,7 @@ typedef enum {
  * per launch over the average launch time in GB/s (READ: the array once;
  * COPY: twice; PULL48: 2 x 48 x elem_bytes per interior site) to *gbs and
  * that time in microseconds to *us (either may be NULL).  RLBM_EINVAL for
- * nx or ny <= 10, ny > 65545, an array beyond 2^34 bytes, elem_bytes other
+ * nx <= 12 or ny <= 10, ny > 65545, an odd nx for PULL48_PAIR, an array beyond 2^34 bytes, elem_bytes other
  * than 2, 4 or 8, reps < 1 or an unknown pattern; RLBM_ENOMEM if the arrays
  * do not fit; synchronises the stream. */
 rlbm_status rlbm_bandwidth_probe(int pattern, int elem_bytes, int nx, int ny, int nontemporal, int reps,

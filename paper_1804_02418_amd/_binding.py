@@ -437,7 +437,7 @@ class NotFound(RlbmError):
     pass
 
 
-PROBE_PATTERNS = {"read": 0, "copy": 1, "pull48": 2}
+PROBE_PATTERNS = {"read": 0, "copy": 1, "pull48": 2, "pull48_pair": 3}
 
 
 def bandwidth_probe(pattern: str, elem_bytes: int, nx: int, ny: int, nontemporal: bool = False, reps: int = 10,

@@ -95,6 +95,84 @@ __global__ __launch_bounds__(256) void probe_pull48(const T *__restrict__ src, T
     }
 }
 
+// Two adjacent interior sites per thread (x even): each of the 48 planes is
+// read as one two-element vector from the hop-shifted pair address (aligned
+// to the element only, for odd hops) and written as one aligned vector.
+template <class T>
+struct Pair;
+template <>
+struct Pair<_Float16> {
+    typedef unsigned int V __attribute__((aligned(2)));
+    __device__ static float lo(V v) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu)); }
+    __device__ static float hi(V v) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16)); }
+    __device__ static V make(float a, float b)
+    {
+        return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)a) |
+               ((unsigned)__builtin_bit_cast(unsigned short, (_Float16)b) << 16);
+    }
+};
+typedef float pair_f32 __attribute__((ext_vector_type(2)));
+typedef double pair_f64 __attribute__((ext_vector_type(2)));
+template <>
+struct Pair<float> {
+    typedef pair_f32 V __attribute__((aligned(4)));
+    __device__ static float lo(V v) { return v.x; }
+    __device__ static float hi(V v) { return v.y; }
+    __device__ static V make(float a, float b) { return V{a, b}; }
+};
+template <>
+struct Pair<double> {
+    typedef pair_f64 V __attribute__((aligned(8)));
+    __device__ static float lo(V v) { return (float)v.x; }
+    __device__ static float hi(V v) { return (float)v.y; }
+    __device__ static V make(float a, float b) { return V{(double)a, (double)b}; }
+};
+
+template <class T, bool NT>
+__global__ __launch_bounds__(256) void probe_pull48_pair(const T *__restrict__ src, T *__restrict__ dst, int nx,
+                                                         int ny, long long P)
+{
+    typedef typename Pair<T>::V V;
+    const int x = 2 * (blockIdx.x * 256 + threadIdx.x);
+    const int y = kReach + blockIdx.y;
+    if (x < kReach + 1 || x + 1 >= nx - kReach || y >= ny - kReach) return;
+    const long long site = (long long)y * nx + x;
+    float h[2 * kQ];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int d = i / kShells;
+        const V v = *reinterpret_cast<const V *>(src + ((long long)i * P + site - ((long long)kCy[d] * nx + kCx[d])));
+        h[2 * i] = Pair<T>::lo(v);
+        h[2 * i + 1] = Pair<T>::hi(v);
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < 2 * kQ; ++i) s += h[i];
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const V v = Pair<T>::make(0.5f * h[2 * i] + 1e-9f * s, 0.5f * h[2 * i + 1] + 1e-9f * s);
+        V *q = reinterpret_cast<V *>(dst + ((long long)i * P + site));
+        if constexpr (NT)
+            __builtin_nontemporal_store(v, q);
+        else
+            *q = v;
+    }
+}
+
+template <class T>
+hipError_t launch_pull_pair(const void *a, void *b, int nx, int ny, int nt, hipStream_t s)
+{
+    const dim3 grid((unsigned)((nx / 2 + 255) / 256), (unsigned)(ny - 2 * kReach));
+    const long long P = (long long)nx * ny;
+    if (nt)
+        hipLaunchKernelGGL((probe_pull48_pair<T, true>), grid, dim3(256), 0, s, static_cast<const T *>(a),
+                           static_cast<T *>(b), nx, ny, P);
+    else
+        hipLaunchKernelGGL((probe_pull48_pair<T, false>), grid, dim3(256), 0, s, static_cast<const T *>(a),
+                           static_cast<T *>(b), nx, ny, P);
+    return hipGetLastError();
+}
+
 template <class T>
 hipError_t launch_pull(const void *a, void *b, int nx, int ny, int nt, hipStream_t s)
 {
@@ -120,8 +198,9 @@ rlbm_status probe_fail(rlbm_status st, const char *what, hipError_t e)
 extern "C" rlbm_status rlbm_bandwidth_probe(int pattern, int elem_bytes, int nx, int ny, int nontemporal, int reps,
                                             void *hip_stream, double *gbs, double *us)
 {
-    if (pattern < RLBM_PROBE_READ || pattern > RLBM_PROBE_PULL48 || (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) ||
-        nx <= 2 * kReach || ny <= 2 * kReach || ny - 2 * kReach > 65535 || reps < 1)
+    if (pattern < RLBM_PROBE_READ || pattern > RLBM_PROBE_PULL48_PAIR ||
+        (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) || nx <= 2 * kReach + 2 || ny <= 2 * kReach ||
+        ny - 2 * kReach > 65535 || reps < 1 || (pattern == RLBM_PROBE_PULL48_PAIR && nx % 2))
         return set_error(RLBM_EINVAL, "rlbm_bandwidth_probe: invalid pattern, element size, size or repetitions");
     const size_t bytes = (size_t)kQ * (size_t)nx * (size_t)ny * (size_t)elem_bytes;
     if (bytes > (1ull << 34)) return set_error(RLBM_EINVAL, "rlbm_bandwidth_probe: array beyond 2^34 bytes");
@@ -155,6 +234,10 @@ extern "C" rlbm_status rlbm_bandwidth_probe(int pattern, int elem_bytes, int nx,
         }
         const void *from = (k & 1) ? b : a;
         void *to = (k & 1) ? a : b;
+        if (pattern == RLBM_PROBE_PULL48_PAIR)
+            return elem_bytes == 2 ? launch_pull_pair<_Float16>(from, to, nx, ny, nontemporal, s)
+                   : elem_bytes == 4 ? launch_pull_pair<float>(from, to, nx, ny, nontemporal, s)
+                                     : launch_pull_pair<double>(from, to, nx, ny, nontemporal, s);
         return elem_bytes == 2 ? launch_pull<_Float16>(from, to, nx, ny, nontemporal, s)
                : elem_bytes == 4 ? launch_pull<float>(from, to, nx, ny, nontemporal, s)
                                  : launch_pull<double>(from, to, nx, ny, nontemporal, s);
@@ -175,7 +258,10 @@ extern "C" rlbm_status rlbm_bandwidth_probe(int pattern, int elem_bytes, int nx,
     (void)hipFree(sink);
     if (ee != hipSuccess) return probe_fail(RLBM_EDEVICE, "device", ee);
     const double t = (double)ms / reps * 1e-3;
-    const double interior = (double)(nx - 2 * kReach) * (double)(ny - 2 * kReach);
+    // the pair pattern covers the pairs (x, x + 1), x even, inside [6, nx - 5)
+    const double interior = (double)(pattern == RLBM_PROBE_PULL48_PAIR ? 2 * ((nx - kReach - 1 - (kReach + 1)) / 2)
+                                                                        : nx - 2 * kReach) *
+                             (double)(ny - 2 * kReach);
     const double moved = pattern == RLBM_PROBE_READ   ? (double)bytes
                          : pattern == RLBM_PROBE_COPY ? 2.0 * (double)bytes
                                                       : 2.0 * kQ * elem_bytes * interior;

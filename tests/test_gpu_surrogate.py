@@ -155,6 +155,67 @@ def test_network_forward_and_backward_match_reference():
     assert cos > 0.999 and rel < 5e-2
 
 
+def test_conditioned_network_gradient_element_by_element():
+    """The same 32 x 32 network conditioned so that it takes no ReLU decision
+    near zero (weights x 1/8, biases +1; every reference activation above
+    0.05): its gradient must match the reference's, which stores every
+    activation in bfloat16 as the kernels do, element by element -- within
+    2% of each element plus 0.5% of the layer's largest (the floor covers
+    elements whose terms cancel down to the size of their rounding)."""
+    import paper_1804_02418_amd as rl
+
+    torch = _torch()
+    base, cin, cout, theta, x, t = _net_case()
+    off = 0
+    for _, ci, co, k in S.layer_list(base, cin, cout):
+        n = co * k * k * ci
+        theta[off:off + n] *= 0.125
+        theta[off + n:off + n + co] = 1.0
+        off += n + co
+    B, H, W = x.shape[:3]
+    net = rl.UNet(base, cin, cout, H, W, max_batch=B)
+    net.set_params(theta.astype(np.float32))
+    xb = _bf16_round(x)
+    y = torch.empty((B, H, W, cout), dtype=torch.float32, device="cuda")
+    net.forward(torch.from_numpy(xb.astype(np.float32)).cuda(), y)
+    dy = np.random.default_rng(3).normal(size=(B, H, W, cout)) + 0.5
+    dx = torch.empty((B, H, W, cin), dtype=torch.float32, device="cuda")
+    net.zero_grad()
+    net.backward(torch.from_numpy(dy.astype(np.float32)).cuda(), dx)
+    g = net.get_grads().astype(np.float64)
+    net.close()
+    ref = S.ReferenceUNet(base, cin, cout, store=S.bf16_round)
+    tb = _kernel_params(theta, base, cin, cout)
+    yr, cache = ref.forward(tb, xb)
+    names = [l[0] for l in S.layer_list(base, cin, cout)]
+    amin = min(float(cache[n][1].min()) for n in names[:-1])
+    assert amin > 0.05, amin
+    gr, dxr = ref.backward(tb, cache, dy)
+    worst = _elementwise(g, gr, base, cin, cout, rtol=2e-2, floor=5e-3)
+    gdx = dx.cpu().numpy().astype(np.float64)
+    wdx = float(np.max(np.abs(gdx - dxr) / (2e-2 * np.abs(dxr) + 5e-3 * np.abs(dxr).max())))
+    print("32x32 conditioned: min activation", amin, "element-wise worst ratio per layer",
+          {k: round(v, 3) for k, v in worst.items()}, "input", round(wdx, 3), flush=True)
+    assert max(worst.values()) <= 1.0, worst
+    assert wdx <= 1.0
+
+
+def _elementwise(g, gr, base, cin, cout, rtol, floor):
+    """Per layer, weights and biases apart: every element of the gradient g
+    within rtol of the reference's element plus floor times the layer's
+    largest reference element (the floor covers the elements whose terms
+    cancel down to the size of their rounding).  Returns the worst ratio of
+    error to allowance per layer."""
+    Pg, Pr = S.unpack(g, base, cin, cout), S.unpack(gr, base, cin, cout)
+    worst = {}
+    for n in Pr:
+        for j, tag in ((0, "w"), (1, "b")):
+            a, r = Pg[n][j], Pr[n][j]
+            allow = rtol * np.abs(r) + floor * np.abs(r).max()
+            worst[f"{n}.{tag}"] = float(np.max(np.abs(a - r) / allow))
+    return worst
+
+
 def _kernel_params(theta, base, cin, cout):
     """Parameters as the kernels use them: weights in bfloat16, biases in FP32."""
     out = theta.astype(np.float64).copy()
@@ -245,9 +306,15 @@ def test_network_at_bench_size_matches_reference():
     edx = float(np.linalg.norm(gdx[3] - dxr[0]) / np.linalg.norm(dxr))
     print("256x256 conditioned: min activation", amin, "input gradient", edx, "per layer (weights, biases)", errs,
           flush=True)
+    worst = _elementwise(g, gr, base, cin, cout, rtol=2e-2, floor=5e-3)
+    wdx = float(np.max(np.abs(gdx[3] - dxr[0]) / (2e-2 * np.abs(dxr[0]) + 5e-3 * np.abs(dxr).max())))
+    print("element-wise worst ratio per layer", {k: round(v, 3) for k, v in worst.items()}, "input", wdx,
+          flush=True)
     for n, e in errs.items():
         assert max(e) <= 2e-2, (n, e)
     assert edx <= 2e-2
+    assert max(worst.values()) <= 1.0, worst
+    assert wdx <= 1.0
     assert not np.any(np.delete(gdx, 3, axis=0))
 
 
