@@ -217,7 +217,10 @@ rlbm_status build_gather_table(rlbm_lattice *L, const std::vector<signed char> &
     L->gtab = nullptr;
     L->gtab_rows = 0;
     const long long P = L->plane();
-    if (P * kQ >= (1LL << 31)) return RLBM_OK;  // computed gather for huge lattices
+    // computed gather for huge lattices: table codes are 31-bit element
+    // indices, and the kernels that read a table address every population
+    // as a 32-bit byte offset from the array
+    if (P * kQ >= (1LL << 31) || P * kQ * (long long)store_bytes(L->storage) >= (1LL << 32)) return RLBM_OK;
     const int nx = L->nx, ny = L->ny;
     const bool all = !has_interior(nx, ny, L->mask != nullptr);
     const long long nb = boundary_count(nx, ny, all);

@@ -70,6 +70,22 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *plane_at(T *base
     return (GT *)((GC *)base + site * (unsigned)sizeof(T));
 }
 
+// The same from a byte offset held in a register.  The stores of the step
+// come after the Landau solve's branches, in other basic blocks than the
+// one that formed the site's offset, and there the compiler sees only a
+// 64-bit value and forms a 64-bit address per lane and store (48 vector
+// instructions per site).  The caller passes the offset through an empty
+// asm in the store's own block, so that it is a fresh 32-bit value there and
+// the store takes the scalar-base plus 32-bit-offset form.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *plane_at_bytes(T *base, unsigned byte_offset)
+{
+    asm("" : "+s"(base));
+    typedef __attribute__((address_space(1))) T GT;
+    typedef __attribute__((address_space(1))) const char GC;
+    return (GT *)((GC *)base + byte_offset);
+}
+
 // Reciprocal and reciprocal square root in float64 from the hardware
 // estimates (about 23 correct bits) and two Newton steps each, which leave
 // a few units in the last place: the Landau solve and the density factors
@@ -326,24 +342,46 @@ __device__ __forceinline__ void gather_general(const StepArgs<R> &A, const S *__
 // The source row is always inside the lattice here.  Each load picks its
 // address per lane (no lane skips a load), and the contact equilibria, when
 // the side has contact spans at all, replace values afterwards.
-template <class S, class R>
+// OFF32: the whole population array is below 4 GiB (every lattice that has
+// a boundary gather table), so every element is a 32-bit byte offset from
+// src: the loads take the scalar-base plus 32-bit-offset form and the
+// address arithmetic stays in 32 bits (instead of a 64-bit address per lane
+// and population).
+template <class S, class R, bool OFF32>
 __device__ __forceinline__ void side_wave_gather(const StepArgs<R> &A, const S *__restrict__ src, int x, int y,
                                                  unsigned site, R (&h)[kQ])
 {
     const int nx = A.nx;
     const long long P = A.plane;
+    if constexpr (OFF32) {
+        const unsigned Pu = (unsigned)P;
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-        const int d = i / kShells;
-        const int sx = x - kCx[d];
-        long long e = (long long)i * P + (long long)(y - kCy[d]) * nx + sx;  // plain pull
-        if (kCx[d] != 0) {
-            const bool out = (unsigned)sx >= (unsigned)nx;
-            const long long wrapped = e + (sx < 0 ? nx : -nx);
-            const long long bounce = (long long)(kShells * ((d + kDirs / 2) % kDirs) + (i % kShells)) * P + site;
-            e = out ? (A.periodic_x ? wrapped : bounce) : e;
+        for (int i = 0; i < kQ; ++i) {
+            const int d = i / kShells;
+            const int sx = x - kCx[d];
+            unsigned e = (unsigned)i * Pu + (unsigned)((y - kCy[d]) * nx + sx);  // plain pull
+            if (kCx[d] != 0) {
+                const bool out = (unsigned)sx >= (unsigned)nx;
+                const unsigned wrapped = e + (unsigned)(sx < 0 ? nx : -nx);
+                const unsigned bounce = (unsigned)(kShells * ((d + kDirs / 2) % kDirs) + (i % kShells)) * Pu + site;
+                e = out ? (A.periodic_x ? wrapped : bounce) : e;
+            }
+            h[i] = StoreIO<S>::template load<R>(plane_at_bytes(src, e * (unsigned)sizeof(S)));
         }
-        h[i] = StoreIO<S>::template load<R>(src + e);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+            const int d = i / kShells;
+            const int sx = x - kCx[d];
+            long long e = (long long)i * P + (long long)(y - kCy[d]) * nx + sx;  // plain pull
+            if (kCx[d] != 0) {
+                const bool out = (unsigned)sx >= (unsigned)nx;
+                const long long wrapped = e + (sx < 0 ? nx : -nx);
+                const long long bounce = (long long)(kShells * ((d + kDirs / 2) % kDirs) + (i % kShells)) * P + site;
+                e = out ? (A.periodic_x ? wrapped : bounce) : e;
+            }
+            h[i] = StoreIO<S>::template load<R>(src + e);
+        }
     }
     if (!A.periodic_x && A.side_contacts) {
 #pragma unroll
@@ -455,7 +493,8 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
                 for (int i = 0; i < 8; ++i) {
                     const unsigned code = c[cur][i];
                     const bool contact = (code & kContactFlag) != 0;
-                    h[i0 + i] = StoreIO<S>::template load<R>(src + (contact ? 0u : code));
+                    h[i0 + i] = StoreIO<S>::template load<R>(
+                        plane_at_bytes(src, (contact ? 0u : code) * (unsigned)sizeof(S)));
                     any = any || contact;
                 }
                 if (__ballot(any)) {
@@ -471,7 +510,16 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
             gather_general<S, R>(A, src, x, y, site, h);
         }
     } else if (side_wave) {
-        side_wave_gather<S, R>(A, src, x, y, site, h);
+        if constexpr (GATHER == kGatherTable) {
+            side_wave_gather<S, R, true>(A, src, x, y, site, h);
+        } else if constexpr (GATHER == kGatherEither) {
+            if (A.gather_tab)
+                side_wave_gather<S, R, true>(A, src, x, y, site, h);
+            else
+                side_wave_gather<S, R, false>(A, src, x, y, site, h);
+        } else {
+            side_wave_gather<S, R, false>(A, src, x, y, site, h);
+        }
     } else {
         // uniform plane base pointers + one 32-bit site offset
 #pragma unroll
@@ -484,8 +532,10 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
     // ---- collide; each post-collision value is stored as soon as it is
     // formed (streaming stores bypass the caches: the next step reads every
     // value once) ----
+    unsigned site_bytes = site * (unsigned)sizeof(S);
     auto store = [&](int i, R v) {
-        auto p = plane_at(dst + (long long)i * P, site);
+        asm volatile("" : "+v"(site_bytes));
+        auto p = plane_at_bytes(dst + (long long)i * P, site_bytes);
         if constexpr (NT)
             StoreIO<S>::template store_nt<R>(p, v);
         else

@@ -132,9 +132,19 @@ def test_graphene_sample_full_size_one_step_from_gpu_state():
 
 def test_graphene_sample_full_size_200_steps_matches_oracle():
     """1024 x 512 graphene sample, FP64, 200 steps on both sides from the
-    uniform start.  n holds 1e-12 relative.  The velocity stays below 4e-4
-    here, and rounding-order differences of a few units in the last place of
-    the unit-scale four-velocity remain; u is held to 1e-13 absolute."""
+    uniform start, every site.  n and eps hold 1e-12 relative.  The velocity
+    (below 4e-4 here) is the small difference of unit-scale populations, and
+    over 200 steps no float64 evaluation holds it to 1e-12 of its maximum:
+    the oracle itself departs from the same oracle built in long double by
+    err_u = 6.3e-12 (stored with the oracle fields of this run,
+    tests/golden/graphene_1024x512_t200.npz).  u is held to five times that
+    floor, as in test_gpu_longrun.py."""
+    import json
+    import os
+
+    meta = json.loads(str(np.load(os.path.join(os.path.dirname(__file__), "golden",
+                                               "graphene_1024x512_t200.npz"))["meta"]))
+    bound = 5.0 * meta["floor"]["err_u"]
     w = workloads.graphene_sample(storage="f64")
     O = oracle_lattice(w)
     G = gpu_lattice(w, "f64")
@@ -144,9 +154,8 @@ def test_graphene_sample_full_size_200_steps_matches_oracle():
     got = G.read_fields()
     G.close()
     e = field_errors(got, ref)
-    du = float(np.max(np.hypot(got["vx"] - ref["vx"], got["vy"] - ref["vy"])))
-    _say("graphene 1024x512 200 steps", e, "abs u", du)
-    assert e["err_n"] <= TOL and e["err_eps"] <= TOL and du <= 1e-13
+    _say("graphene 1024x512 200 steps", e, "floor", meta["floor"]["err_u"], "bound", bound)
+    assert e["err_n"] <= TOL and e["err_eps"] <= TOL and e["err_u"] <= bound
 
 
 def test_checkpoint_restore_is_bit_identical():
