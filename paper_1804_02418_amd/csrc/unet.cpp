@@ -147,12 +147,15 @@ void *layer_input_grad(rlbm_unet *N, int i)
     }
 }
 
-rlbm_status conv_fwd(rlbm_unet *N, int i, int B)
+rlbm_status conv_fwd(rlbm_unet *N, int i, int B, const ConvInputs *extra = nullptr)
 {
     const Layer &l = N->L[i];
     const char *wbf = static_cast<const char *>(N->theta_bf) + 2 * l.woff;
-    UTRY(conv3x3_forward(layer_input(N, i), wbf, N->theta + l.boff, N->act[i], B, N->lh(l.level), N->lw(l.level), l.ci,
-                         l.co, true, N->stream));
+    ConvInputs x;
+    if (extra) x = *extra;
+    if (!x.skip) x.in = layer_input(N, i);
+    UTRY(conv3x3_forward_ex(x, wbf, N->theta + l.boff, N->act[i], B, N->lh(l.level), N->lw(l.level), l.ci, l.co, true,
+                            N->stream));
     return RLBM_OK;
 }
 
@@ -357,26 +360,48 @@ rlbm_status rlbm_unet_forward(rlbm_unet *N, const float *x, float *y, int batch)
         rlbm_status s2 = conv_fwd(N, a, B);
         return s2 ? s2 : conv_fwd(N, b, B);
     };
-    if ((st = block(E1A, E1B))) return st;
-    UTRY(pool_forward(N->act[E1B], N->pool[1], B, N->lh(0), N->lw(0), c0, N->stream));
-    if ((st = block(E2A, E2B))) return st;
-    UTRY(pool_forward(N->act[E2B], N->pool[2], B, N->lh(1), N->lw(1), c1, N->stream));
-    if ((st = block(E3A, E3B))) return st;
-    UTRY(pool_forward(N->act[E3B], N->pool[3], B, N->lh(2), N->lw(2), c2, N->stream));
-    if ((st = block(E4A, E4B))) return st;
-    UTRY(pool_forward(N->act[E4B], N->pool[4], B, N->lh(3), N->lw(3), c3, N->stream));
+    // The pooled inputs of levels 1..4 come out of the last convolution of
+    // the level above, the decoder's concatenations are read in place by its
+    // first convolution, and the head rides on the last one.
+    auto enc = [&](int a, int b, int level) {
+        rlbm_status s2 = conv_fwd(N, a, B);
+        if (s2) return s2;
+        ConvInputs io;
+        io.pooled = N->pool[level + 1];
+        return conv_fwd(N, b, B, &io);
+    };
+    auto dec = [&](int a, int b, int up, int skip, int level, int cu) {
+        ConvInputs io;
+        io.in = N->act[up];
+        io.skip = N->act[skip];
+        io.cu = cu;
+        io.cat = N->cat[level];
+        rlbm_status s2 = conv_fwd(N, a, B, &io);
+        return s2 ? s2 : conv_fwd(N, b, B);
+    };
+    if ((st = enc(E1A, E1B, 0))) return st;
+    if ((st = enc(E2A, E2B, 1))) return st;
+    if ((st = enc(E3A, E3B, 2))) return st;
+    if ((st = enc(E4A, E4B, 3))) return st;
     if ((st = block(BA, BB))) return st;
-    UTRY(up_concat(N->act[BB], N->act[E4B], N->cat[3], B, N->lh(3), N->lw(3), c3, c3, N->stream));
-    if ((st = block(D4A, D4B))) return st;
-    UTRY(up_concat(N->act[D4B], N->act[E3B], N->cat[2], B, N->lh(2), N->lw(2), c3, c2, N->stream));
-    if ((st = block(D3A, D3B))) return st;
-    UTRY(up_concat(N->act[D3B], N->act[E2B], N->cat[1], B, N->lh(1), N->lw(1), c2, c1, N->stream));
-    if ((st = block(D2A, D2B))) return st;
-    UTRY(up_concat(N->act[D2B], N->act[E1B], N->cat[0], B, N->lh(0), N->lw(0), c1, c0, N->stream));
-    if ((st = block(D1A, D1B))) return st;
+    if ((st = dec(D4A, D4B, BB, E4B, 3, c3))) return st;
+    if ((st = dec(D3A, D3B, D4B, E3B, 2, c3))) return st;
+    if ((st = dec(D2A, D2B, D3B, E2B, 1, c2))) return st;
     const Layer &h = N->L[HEAD];
-    UTRY(head_forward(N->act[D1B], static_cast<const char *>(N->theta_bf) + 2 * h.woff, N->theta + h.boff, y,
-                      (long long)px(N, 0, B), h.ci, h.co, N->stream));
+    {
+        ConvInputs io;
+        io.in = N->act[D2B];
+        io.skip = N->act[E1B];
+        io.cu = c1;
+        io.cat = N->cat[0];
+        if ((st = conv_fwd(N, D1A, B, &io))) return st;
+        ConvInputs hx;
+        hx.head_w = static_cast<const char *>(N->theta_bf) + 2 * h.woff;
+        hx.head_b = N->theta + h.boff;
+        hx.head_out = y;
+        hx.head_o = h.co;
+        if ((st = conv_fwd(N, D1B, B, &hx))) return st;
+    }
     N->last_batch = B;
     return RLBM_OK;
 }
@@ -402,6 +427,12 @@ rlbm_status rlbm_unet_backward(rlbm_unet *N, const float *dy, int batch, float *
     const int c0 = N->base, c1 = 2 * c0, c2 = 4 * c0, c3 = 8 * c0;
     const Layer &h = N->L[HEAD];
     UTRY(conv3x3_adjoint_weights_all(N->theta_bf, N->wt, N->adj, N->stream));
+    // the forward read the decoder's concatenations in place; the weight
+    // gradients of the decoder's first convolutions want them formed
+    UTRY(up_concat(N->act[BB], N->act[E4B], N->cat[3], B, N->lh(3), N->lw(3), c3, c3, N->stream));
+    UTRY(up_concat(N->act[D4B], N->act[E3B], N->cat[2], B, N->lh(2), N->lw(2), c3, c2, N->stream));
+    UTRY(up_concat(N->act[D3B], N->act[E2B], N->cat[1], B, N->lh(1), N->lw(1), c2, c1, N->stream));
+    UTRY(up_concat(N->act[D2B], N->act[E1B], N->cat[0], B, N->lh(0), N->lw(0), c1, c0, N->stream));
     UTRY(head_backward(dy, N->act[D1B], static_cast<const char *>(N->theta_bf) + 2 * h.woff, N->gact[D1B], N->part,
                        N->grad + h.woff, N->grad + h.boff, (long long)px(N, 0, B), h.ci, h.co, N->stream));
     rlbm_status st;

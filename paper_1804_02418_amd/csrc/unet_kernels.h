@@ -9,6 +9,20 @@ namespace rlbm {
 // out = act(conv3x3(in, w) + bias), zero padding, BF16 in/out, FP32 accumulation (Ci, Co multiples of 16).
 hipError_t conv3x3_forward(const void *in, const void *w, const float *bias, void *out, int B, int H, int W, int Ci,
                            int Co, bool relu, hipStream_t s);
+// The input and the optional extra outputs of a forward convolution.
+struct ConvInputs {
+    const void *in = nullptr;    // B x H x W x Ci; with skip: B x H/2 x W/2 x cu, upsampled 2x (nearest)
+    const void *skip = nullptr;  // with skip, the input is [up(in) | skip], skip B x H x W x (Ci - cu)
+    int cu = 0;
+    void *cat = nullptr;         // B x H x W x Ci, where the concatenation is formed when it cannot be read in place
+    void *pooled = nullptr;      // also write the 2x2 average of the output, B x H/2 x W/2 x Co
+    const void *head_w = nullptr;  // also apply a 1x1 head (BF16 head_o x Co weights, FP32 bias) to the output
+    const float *head_b = nullptr;
+    float *head_out = nullptr;   // B x H x W x head_o, FP32
+    int head_o = 0;
+};
+hipError_t conv3x3_forward_ex(const ConvInputs &x, const void *w, const float *bias, void *out, int B, int H, int W,
+                              int Ci, int Co, bool relu, hipStream_t s);
 // wt[ci][8 - tap][co] = w[co][tap][ci]; the gradient with respect to the input of a 3x3
 // convolution is conv3x3_forward(dout, wt) (no bias, no activation).
 hipError_t conv3x3_adjoint_weights(const void *w, void *wt, int Ci, int Co, hipStream_t s);

@@ -27,116 +27,281 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-template <int KSTEP>
-struct Mfma;
-template <>
-struct Mfma<32> {
-    typedef bf16x8 vec;
-    __device__ static f32x4 run(vec a, vec b, f32x4 c) { return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0); }
-};
-template <>
-struct Mfma<16> {
-    typedef bf16x4 vec;
-    __device__ static f32x4 run(vec a, vec b, f32x4 c)
-    {
-        typedef __attribute__((__vector_size__(4 * sizeof(short)))) short s4;
-        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4, a), __builtin_bit_cast(s4, b), c, 0, 0,
-                                                         0);
-    }
-};
-
 // ---------------------------------------------------------------- conv 3x3
 
-// grid.x = B * ceil(H / ROWS) * ceil(W / 64), grid.y = Co / 16; 4
-// wavefronts per block, wavefront w covers pixels x0 + 16 w ... + 15 of
-// ROWS consecutive output rows.  The block stages the ROWS + 2 input rows it
-// needs (66 pixels: the segment and one on each side, zero outside the
-// image) and its 16 output channels' weights through LDS, CC input channels
-// at a time (16, 32 or 64: the LDS a block holds follows the layer's width,
-// so narrow layers keep more blocks resident), so that every input value is
-// fetched once per block instead of once per tap and wavefront, and each
-// staged row serves up to three output rows.
-template <int KSTEP, bool RELU, int ROWS, int CC>
-__global__ __launch_bounds__(256) void conv3x3_fwd_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ w,
-                                                          const float *__restrict__ bias, bf16 *__restrict__ out,
-                                                          int H, int W, int Ci, int Co)
+// Geometry of one forward-convolution launch, computed on the host.  A
+// block computes a patch of 64 * ROWS pixels of one image -- pr rows of pw
+// pixels, pw = 64, or 32 or 16 when the image is that narrow -- for NB
+// output channels.
+struct ConvGeom {
+    int H, W, Ci, Co;
+    int pw_log2;        // log2 of the patch width pw
+    int xw;             // staged row length, pw + 2 (one halo pixel each side)
+    unsigned xw_magic;  // floor(2^32 / xw) + 1: p / xw == umulhi(p, xw_magic) for p < 2^16
+    int patches_x, patches_y;
+    int relu;
+    int cu;      // input channels read from `in` (Ci, or the upsampled part of a concatenation)
+    int head_o;  // outputs of a fused 1x1 head (0: none)
+};
+
+// out[p][co] = act(bias[co] + sum_{tap, ci} in[p + tap][ci] W[co][tap][ci]).
+// grid.x = B * patches_y * patches_x, grid.y = Co / NB, 4 wavefronts.
+//
+// Input.  The input channels are taken CC at a time (a chunk): the block
+// stages the chunk's (pr + 2) x (pw + 2) input pixels (zero outside the
+// image) and its NB x 9 x CC weights through LDS.  Every 16-byte global load
+// of a chunk is issued before the first LDS write, and the next chunk's loads
+// are in flight while the matrix instructions consume the current one.  With
+// CAT the input is the concatenation [nearest 2x upsampling of in | skip]
+// (in: H/2 x W/2 x cu, skip: H x W x (Ci - cu)), read in place: a chunk lies
+// wholly in one of the two.
+//
+// Product.  The K dimension of a chunk, 9 taps x CC channels, is walked 32 at
+// a time with v_mfma_f32_16x16x32_bf16 (for CC = 16 a step spans two taps;
+// the last step's missing tenth tap has zero weights).  Wavefront w owns the
+// 16-pixel groups w, w + 4, ... of the patch and all NB channels: per step it
+// reads ROWS pixel fragments and NB / 16 weight fragments and issues
+// ROWS * NB / 16 matrix instructions.  The weights are the A operand, so a
+// lane's accumulator holds 4 consecutive output channels of one pixel.
+//
+// Output.  The activated tile goes through LDS (BF16, as stored) and leaves
+// in 16-byte stores; from the same tile the block can also write the 2x2
+// average of its output (pooled: H/2 x W/2 x Co; pr and pw even) and a 1x1
+// head (head_out[p][o] = head_b[o] + sum_c out[p][c] head_w[o][c], FP32;
+// NB == Co).
+template <int ROWS, int NB, int CC, bool CAT>
+__global__ __launch_bounds__(256) void conv3x3_fwd_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ skip,
+                                                          const bf16 *__restrict__ w, const float *__restrict__ bias,
+                                                          bf16 *__restrict__ out, bf16 *__restrict__ pooled,
+                                                          const bf16 *__restrict__ head_w,
+                                                          const float *__restrict__ head_b, float *__restrict__ head_out,
+                                                          const ConvGeom g)
 {
-    typedef typename Mfma<KSTEP>::vec vec;
-    constexpr int KPL = KSTEP / 4;  // channels per lane per K step
-    constexpr int CP = CC + 8;      // CC channels per chunk, padded row (fewer bank conflicts)
-    __shared__ __attribute__((aligned(16))) bf16 Xs[ROWS + 2][66][CP];
-    __shared__ __attribute__((aligned(16))) bf16 Ws[16][9][CP];
+    constexpr int G = CC / 8;                   // 16-byte groups per staged pixel
+    constexpr int CP = CC + 8;                  // staged pixel stride (16 bytes of padding: no bank conflicts)
+    constexpr int XPIX = (ROWS + 2) * 66;       // staged pixels of the widest patch shape (the most)
+    constexpr int NS = (9 * CC + 31) / 32;      // K steps of 32 per chunk
+    constexpr int WS = 32 * NS + 8;             // staged weight row of one output channel, padded
+    constexpr int NT = NB / 16;                 // 16-channel output tiles
+    constexpr int XU = (XPIX * G + 255) / 256;  // 16-byte staging units per thread
+    constexpr int WU = (NB * 9 * G + 255) / 256;
+    constexpr int TS = NB + 8;                  // output tile row (one pixel), padded
+    static_assert(64 * ROWS * TS <= XPIX * CP + NB * WS, "the output tile reuses the staging LDS");
+    __shared__ __attribute__((aligned(16))) bf16 smem[XPIX * CP + NB * WS];
+    bf16 *const Xs = smem;
+    bf16 *const Ws = smem + XPIX * CP;
+
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
-    const int tiles_w = (W + 63) / 64;
-    const int groups_h = (H + ROWS - 1) / ROWS;
+    const int r = lane & 15, kq = lane >> 4;
+    const int pw = 1 << g.pw_log2, pr = (64 * ROWS) >> g.pw_log2;
     int q = blockIdx.x;
-    const int xt = q % tiles_w;
-    q /= tiles_w;
-    const int y0 = (q % groups_h) * ROWS;
-    const int b = q / groups_h;
-    const int xs = xt * 64, x0 = xs + wave * 16;
-    const int co0 = blockIdx.y * 16;
-    const int r = lane & 15;   // A row (pixel) and B column (channel)
-    const int kq = lane >> 4;  // which group of KPL channels
-    f32x4 acc[ROWS];
+    const int px0 = (q % g.patches_x) << g.pw_log2;
+    q /= g.patches_x;
+    const int py0 = (q % g.patches_y) * pr;
+    const int b = q / g.patches_y;
+    const int co0 = blockIdx.y * NB;
+    const int xunits = (pr + 2) * g.xw * G;
+    bf16x8 zero;
 #pragma unroll
-    for (int rr = 0; rr < ROWS; ++rr) acc[rr] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16 z = (bf16)0.f;
-    for (int c0 = 0; c0 < Ci; c0 += CC) {
-        const int cc = Ci - c0 < CC ? Ci - c0 : CC;  // a multiple of 16
-        const int groups = cc / 8;
-        for (int unit = t; unit < (ROWS + 2) * 66 * groups; unit += 256) {
-            const int g = unit % groups, rest = unit / groups;
-            const int u = rest % 66, rr = rest / 66;
-            const int yy = y0 + rr - 1, xx = xs + u - 1;
-            bf16x8 v;
-            if ((unsigned)yy < (unsigned)H && (unsigned)xx < (unsigned)W)
-                v = *reinterpret_cast<const bf16x8 *>(in + (((long long)b * H + yy) * W + xx) * Ci + c0 + 8 * g);
-            else
-                for (int e = 0; e < 8; ++e) v[e] = z;
-            *reinterpret_cast<bf16x8 *>(&Xs[rr][u][8 * g]) = v;
+    for (int e = 0; e < 8; ++e) zero[e] = (bf16)0.f;
+
+    // Staging loads are raw buffer loads: an offset past the end of the
+    // buffer reads zero, which gives the zero padding outside the image and
+    // idle units without branches around the loads.  Byte offsets of each
+    // unit at channel 0 (kOut when the unit reads nothing), fixed for the block.
+    constexpr unsigned kOut = 0x80000000u;
+    const int hs = CAT ? 1 : 0;  // `in` is at half resolution in a concatenation
+    const int cs = g.Ci - g.cu;
+    const __amdgpu_buffer_rsrc_t xrs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(in + (long long)b * (g.H >> hs) * (g.W >> hs) * g.cu), (short)0,
+        (g.H >> hs) * (g.W >> hs) * g.cu * 2, 0x00020000);
+    const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(CAT ? skip + (long long)b * g.H * g.W * cs : in), (short)0, CAT ? g.H * g.W * cs * 2 : 0, 0x00020000);
+    const __amdgpu_buffer_rsrc_t wrs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(w + (long long)co0 * 9 * g.Ci), (short)0, NB * 9 * g.Ci * 2, 0x00020000);
+    unsigned xo[XU], so[CAT ? XU : 1], wo[WU];
+#pragma unroll
+    for (int i = 0; i < XU; ++i) {
+        const int u = t + 256 * i;
+        const unsigned p = (unsigned)u / G;
+        const int row = (int)__umulhi(p, g.xw_magic);
+        const int yy = py0 - 1 + row, xx = px0 - 1 + ((int)p - row * g.xw);
+        const bool in_img = u < xunits && (unsigned)yy < (unsigned)g.H && (unsigned)xx < (unsigned)g.W;
+        if constexpr (CAT) {
+            xo[i] = in_img ? (unsigned)((((yy >> 1) * (g.W >> 1) + (xx >> 1)) * g.cu + 8 * (u % G)) * 2) : kOut;
+            so[i] = in_img ? (unsigned)(((yy * g.W + xx) * cs + 8 * (u % G)) * 2) : kOut;
+        } else {
+            xo[i] = in_img ? (unsigned)(((yy * g.W + xx) * g.Ci + 8 * (u % G)) * 2) : kOut;
         }
-        for (int unit = t; unit < 16 * 9 * groups; unit += 256) {
-            const int g = unit % groups, rest = unit / groups;
-            const int tap = rest % 9, co = rest / 9;
-            *reinterpret_cast<bf16x8 *>(&Ws[co][tap][8 * g]) =
-                *reinterpret_cast<const bf16x8 *>(w + ((long long)(co0 + co) * 9 + tap) * Ci + c0 + 8 * g);
+    }
+#pragma unroll
+    for (int i = 0; i < WU; ++i) {
+        const int u = t + 256 * i;  // u / G = co * 9 + tap
+        wo[i] = u < NB * 9 * G ? (unsigned)(((u / G) * g.Ci + 8 * (u % G)) * 2) : kOut;
+    }
+    bf16x8 xr[XU], wr[WU];
+    auto load = [&](int c0) {
+        if constexpr (CAT) {
+            const bool fu = c0 < g.cu;  // the whole chunk comes from one source
+            const __amdgpu_buffer_rsrc_t rs = fu ? xrs : srs;
+            const unsigned add = 2 * (fu ? c0 : c0 - g.cu);
+#pragma unroll
+            for (int i = 0; i < XU; ++i)
+                xr[i] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)((fu ? xo[i] : so[i]) + add), 0, 0));
+        } else {
+#pragma unroll
+            for (int i = 0; i < XU; ++i)
+                xr[i] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(xrs, (int)(xo[i] + 2 * c0), 0, 0));
         }
-        __syncthreads();
-        if (x0 < W) {
 #pragma unroll
-            for (int tap = 0; tap < 9; ++tap) {
-                const int dy = tap / 3, dx = tap % 3;
-                for (int k0 = 0; k0 < cc; k0 += KSTEP) {
-                    const vec bv = *reinterpret_cast<const vec *>(&Ws[r][tap][k0 + kq * KPL]);
+        for (int i = 0; i < WU; ++i)
+            wr[i] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(wrs, (int)(wo[i] + 2 * c0), 0, 0));
+    };
+    auto stage = [&]() {
 #pragma unroll
-                    for (int rr = 0; rr < ROWS; ++rr) {
-                        const vec a = *reinterpret_cast<const vec *>(&Xs[rr + dy][wave * 16 + r + dx][k0 + kq * KPL]);
-                        acc[rr] = Mfma<KSTEP>::run(a, bv, acc[rr]);
-                    }
-                }
+        for (int i = 0; i < XU; ++i) {
+            const int u = t + 256 * i;
+            if ((XPIX * G) % 256 == 0 || u < XPIX * G) *reinterpret_cast<bf16x8 *>(&Xs[(u / G) * CP + 8 * (u % G)]) = xr[i];
+        }
+#pragma unroll
+        for (int i = 0; i < WU; ++i) {
+            const int u = t + 256 * i;
+            if ((NB * 9 * G) % 256 == 0 || u < NB * 9 * G) {
+                const int k = u / G, co = k / 9, tap = k - 9 * co;
+                *reinterpret_cast<bf16x8 *>(&Ws[co * WS + tap * CC + 8 * (u % G)]) = wr[i];
             }
         }
-        __syncthreads();
+    };
+    // zero weights for the padding of the last K step (CC = 16 only); never overwritten
+    if constexpr (32 * NS > 9 * CC) {
+        constexpr int PADG = (32 * NS - 9 * CC) / 8;
+        for (int u = t; u < NB * PADG; u += 256)
+            *reinterpret_cast<bf16x8 *>(&Ws[(u / PADG) * WS + 9 * CC + 8 * (u % PADG)]) = zero;
     }
-    if (x0 >= W) return;
-    const int j = lane & 15;
-    const float bj = bias ? bias[co0 + j] : 0.f;
+    // per-lane LDS offsets: the lane's pixel in each of its groups, and the
+    // (tap, channel) of its 8 K values in each step (the padding tap reads tap 8)
+    int xoff[ROWS], toff[NS];
 #pragma unroll
     for (int rr = 0; rr < ROWS; ++rr) {
-        const int y = y0 + rr;
-        if (y >= H) break;
+        const int m = 16 * (4 * rr + wave) + r;
+        xoff[rr] = ((m >> g.pw_log2) * g.xw + (m & (pw - 1))) * CP;
+    }
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int px = x0 + 4 * (lane >> 4) + s;
-            if (px < W) {
-                float v = acc[rr][s] + bj;
-                if (RELU) v = fmaxf(v, 0.f);
-                out[(((long long)b * H + y) * W + px) * Co + co0 + j] = (bf16)v;
+    for (int s = 0; s < NS; ++s) {
+        const int k = 32 * s + 8 * kq;
+        const int tap = k / CC < 9 ? k / CC : 8;
+        toff[s] = ((tap / 3) * g.xw + tap % 3) * CP + k % CC;
+    }
+    const int woff = r * WS + 8 * kq;
+    f32x4 acc[ROWS][NT];
+#pragma unroll
+    for (int rr = 0; rr < ROWS; ++rr)
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) acc[rr][tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    auto compute = [&]() {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            bf16x8 wf[NT];
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt) wf[tt] = *reinterpret_cast<const bf16x8 *>(&Ws[woff + 16 * WS * tt + 32 * s]);
+#pragma unroll
+            for (int rr = 0; rr < ROWS; ++rr) {
+                const bf16x8 xf = *reinterpret_cast<const bf16x8 *>(&Xs[xoff[rr] + toff[s]]);
+#pragma unroll
+                for (int tt = 0; tt < NT; ++tt)
+                    acc[rr][tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[tt], xf, acc[rr][tt], 0, 0, 0);
+            }
+        }
+    };
+
+    load(0);
+    stage();
+    __syncthreads();
+    for (int c0 = CC; c0 < g.Ci; c0 += CC) {
+        load(c0);  // in flight while the current chunk is consumed
+        // keep the loads ahead of the matrix instructions (the scheduler
+        // would otherwise sink them next to their LDS writes)
+        __builtin_amdgcn_sched_barrier(0);
+        compute();
+        __syncthreads();
+        stage();
+        __syncthreads();
+    }
+    compute();
+    __syncthreads();  // the staging LDS becomes the output tile
+
+    // accumulator element e of tile tt: channel co0 + 16 tt + 4 kq + e of the lane's pixel
+    bf16 *const T = smem;
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) {
+        float bv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bv[e] = bias ? bias[co0 + 16 * tt + 4 * kq + e] : 0.f;
+#pragma unroll
+        for (int rr = 0; rr < ROWS; ++rr) {
+            bf16x4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float f = acc[rr][tt][e] + bv[e];
+                if (g.relu) f = fmaxf(f, 0.f);
+                v[e] = (bf16)f;
+            }
+            *reinterpret_cast<bf16x4 *>(&T[(16 * (4 * rr + wave) + r) * TS + 16 * tt + 4 * kq]) = v;
+        }
+    }
+    __syncthreads();
+    constexpr int NG = NB / 8;  // 16-byte groups of a pixel's NB channels
+    for (int u = t; u < 64 * ROWS * NG; u += 256) {
+        const int m = u / NG, gq = u % NG;
+        const int y = py0 + (m >> g.pw_log2), x = px0 + (m & (pw - 1));
+        if (y < g.H && x < g.W)
+            *reinterpret_cast<bf16x8 *>(out + (((long long)b * g.H + y) * g.W + x) * g.Co + co0 + 8 * gq) =
+                *reinterpret_cast<const bf16x8 *>(&T[m * TS + 8 * gq]);
+    }
+    if (pooled) {
+        const int hw = pw >> 1, Ho = g.H >> 1, Wo = g.W >> 1;
+        for (int u = t; u < 16 * ROWS * NG; u += 256) {
+            const int pm = u / NG, gq = u % NG;
+            const int py = pm >> (g.pw_log2 - 1), pxl = pm & (hw - 1);
+            const int Y = (py0 >> 1) + py, X = (px0 >> 1) + pxl;
+            if (Y >= Ho || X >= Wo) continue;
+            const int m00 = 2 * py * pw + 2 * pxl;
+            const bf16x8 p00 = *reinterpret_cast<const bf16x8 *>(&T[m00 * TS + 8 * gq]);
+            const bf16x8 p01 = *reinterpret_cast<const bf16x8 *>(&T[(m00 + 1) * TS + 8 * gq]);
+            const bf16x8 p10 = *reinterpret_cast<const bf16x8 *>(&T[(m00 + pw) * TS + 8 * gq]);
+            const bf16x8 p11 = *reinterpret_cast<const bf16x8 *>(&T[(m00 + pw + 1) * TS + 8 * gq]);
+            bf16x8 o;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                o[e] = (bf16)(0.25f * ((float)p00[e] + (float)p01[e] + (float)p10[e] + (float)p11[e]));
+            *reinterpret_cast<bf16x8 *>(pooled + (((long long)b * Ho + Y) * Wo + X) * g.Co + co0 + 8 * gq) = o;
+        }
+    }
+    if (head_out) {
+        for (int m = t; m < 64 * ROWS; m += 256) {
+            const int y = py0 + (m >> g.pw_log2), x = px0 + (m & (pw - 1));
+            if (y >= g.H || x >= g.W) continue;
+            for (int o = 0; o < g.head_o; ++o) {
+                float sum = head_b[o];
+#pragma unroll
+                for (int c0 = 0; c0 < NB; c0 += 8) {
+                    const bf16x8 xv = *reinterpret_cast<const bf16x8 *>(&T[m * TS + c0]);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) sum += (float)xv[e] * (float)head_w[o * NB + c0 + e];
+                }
+                head_out[(((long long)b * g.H + y) * g.W + x) * g.head_o + o] = sum;
             }
         }
     }
 }
+
+// The instantiated (ROWS, NB, CC): the staging registers (XU + WU units of
+// 4 VGPRs) stay within 24 units and the LDS within 96 KB.
+#define RLBM_CONV_VARIANTS(X)                                                                                   \
+    X(4, 16, 16) X(4, 16, 32) X(4, 16, 64) X(4, 32, 16) X(4, 32, 32) X(4, 32, 64) X(4, 64, 16) X(4, 64, 32)     \
+    X(2, 16, 16) X(2, 16, 32) X(2, 16, 64) X(2, 32, 16) X(2, 32, 32) X(2, 32, 64) X(2, 64, 16) X(2, 64, 32)     \
+    X(1, 16, 16) X(1, 16, 32) X(1, 16, 64) X(1, 16, 128) X(1, 32, 16) X(1, 32, 32) X(1, 32, 64) X(1, 64, 16)    \
+    X(1, 64, 32)
 
 // wt[ci][8 - tap][co] = w[co][tap][ci]: the weights of the adjoint convolution.
 __global__ void conv3x3_adjoint_weights_kernel(const bf16 *__restrict__ w, bf16 *__restrict__ wt, int Ci, int Co)
@@ -741,48 +906,122 @@ inline unsigned grid_for(long long n, int block = 256)
 
 }  // namespace
 
+hipError_t conv3x3_forward_ex(const ConvInputs &x, const void *w, const float *bias, void *out, int B, int H, int W,
+                              int Ci, int Co, bool relu, hipStream_t s)
+{
+    if (Ci % 16 || Co % 16 || B < 1 || H < 1 || W < 1 || !x.in) return hipErrorInvalidValue;
+    // one image's input is addressed with 32-bit byte offsets (buffer loads)
+    if ((long long)H * W * Ci * 2 >= (1LL << 31)) return hipErrorInvalidValue;
+    ConvGeom g;
+    g.H = H;
+    g.W = W;
+    g.Ci = Ci;
+    g.Co = Co;
+    g.pw_log2 = W > 32 ? 6 : W > 16 ? 5 : 4;
+    g.xw = (1 << g.pw_log2) + 2;
+    g.xw_magic = (unsigned)((1ull << 32) / (unsigned)g.xw + 1);  // exact below 2^16 for xw <= 66
+    g.patches_x = (W + (1 << g.pw_log2) - 1) >> g.pw_log2;
+    g.relu = relu ? 1 : 0;
+    g.cu = Ci;
+    g.head_o = 0;
+    // The largest patch x channel tile that still gives 512 blocks (two per
+    // compute unit), else the one with the most blocks.
+    static const int kTiles[][2] = {{4, 64}, {4, 32}, {2, 64}, {4, 16}, {2, 32}, {1, 64}, {2, 16}, {1, 32}, {1, 16}};
+    int rows = 0, nb = 0;
+    long long best = -1;
+    for (const auto &c : kTiles) {
+        if (Co % c[1]) continue;
+        const int pr = (64 * c[0]) >> g.pw_log2;
+        const long long blocks = (long long)B * ((H + pr - 1) / pr) * g.patches_x * (Co / c[1]);
+        if (blocks > best) {
+            best = blocks;
+            rows = c[0];
+            nb = c[1];
+        }
+        if (blocks >= 512) {
+            rows = c[0];
+            nb = c[1];
+            break;
+        }
+    }
+    const int pr = (64 * rows) >> g.pw_log2;
+    g.patches_y = (H + pr - 1) / pr;
+    const long long gx = (long long)B * g.patches_y * g.patches_x;
+    if (gx > 0x7fffffffLL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)gx, (unsigned)(Co / nb));
+
+    // A concatenation is read in place when its two parts are whole chunks
+    // (and the image halves evenly); otherwise it is formed in x.cat first.
+    const bf16 *in = static_cast<const bf16 *>(x.in);
+    const bf16 *skip = nullptr;
+    bool cat = false;
+    int cc = 0;
+    for (int c = 128; c >= 16; c /= 2) {
+        if (Ci % c) continue;
+        if (x.skip && (x.cu % c || (Ci - x.cu) % c)) continue;
+        cc = c;
+        break;
+    }
+    if (x.skip) {
+        if (x.cu < 16 || x.cu >= Ci || x.cu % 16 || H % 2 || W % 2) return hipErrorInvalidValue;
+        if (cc) {
+            cat = true;
+            skip = static_cast<const bf16 *>(x.skip);
+            g.cu = x.cu;
+        } else {
+            if (!x.cat) return hipErrorInvalidValue;
+            hipError_t e = up_concat(x.in, x.skip, x.cat, B, H, W, x.cu, Ci - x.cu, s);
+            if (e != hipSuccess) return e;
+            in = static_cast<const bf16 *>(x.cat);
+            for (int c = 128; c >= 16; c /= 2)
+                if (Ci % c == 0) {
+                    cc = c;
+                    break;
+                }
+        }
+    }
+    // the pooled copy and the head come from the block's output tile when
+    // the patch holds whole 2x2 blocks / all output channels
+    const bool pool_fused = x.pooled && pr % 2 == 0;
+    const bool head_fused = x.head_out && nb == Co;
+    bf16 *o = static_cast<bf16 *>(out);
+    bf16 *pooled = pool_fused ? static_cast<bf16 *>(x.pooled) : nullptr;
+    const bf16 *hw = head_fused ? static_cast<const bf16 *>(x.head_w) : nullptr;
+    float *hout = head_fused ? x.head_out : nullptr;
+    if (head_fused) g.head_o = x.head_o;
+    const bf16 *wt = static_cast<const bf16 *>(w);
+    bool launched = false;
+    // the widest instantiated chunk that fits; every tile has a CC = 16 variant
+    for (int c = cc; c >= 16 && !launched; c /= 2) {
+        if (Ci % c || (cat && (g.cu % c || (Ci - g.cu) % c))) continue;
+#define RLBM_CONV_LAUNCH(R, N, C)                                                                                   \
+    if (!launched && rows == R && nb == N && c == C) {                                                             \
+        if (cat)                                                                                                   \
+            hipLaunchKernelGGL((conv3x3_fwd_kernel<R, N, C, true>), grid, dim3(256), 0, s, in, skip, wt, bias, o,  \
+                               pooled, hw, x.head_b, hout, g);                                                     \
+        else                                                                                                       \
+            hipLaunchKernelGGL((conv3x3_fwd_kernel<R, N, C, false>), grid, dim3(256), 0, s, in, skip, wt, bias, o, \
+                               pooled, hw, x.head_b, hout, g);                                                     \
+        launched = true;                                                                                           \
+    }
+        RLBM_CONV_VARIANTS(RLBM_CONV_LAUNCH)
+#undef RLBM_CONV_LAUNCH
+    }
+    if (!launched) return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (x.pooled && !pool_fused) e = pool_forward(out, x.pooled, B, H, W, Co, s);
+    if (e == hipSuccess && x.head_out && !head_fused)
+        e = head_forward(out, x.head_w, x.head_b, x.head_out, (long long)B * H * W, Co, x.head_o, s);
+    return e;
+}
+
 hipError_t conv3x3_forward(const void *in, const void *w, const float *bias, void *out, int B, int H, int W, int Ci,
                            int Co, bool relu, hipStream_t s)
 {
-    if (Ci % 16 || Co % 16 || B < 1 || H < 1 || W < 1) return hipErrorInvalidValue;
-    const bf16 *i = static_cast<const bf16 *>(in), *wt = static_cast<const bf16 *>(w);
-    bf16 *o = static_cast<bf16 *>(out);
-    // four output rows per block on images of 16 rows or more (each staged
-    // row then serves up to three output rows; measured faster than one row
-    // per block down to the 16 x 16 level of a 256 x 256 network), one on
-    // smaller images; channel chunks of the layer's width up to 64
-    const bool four = H >= 16;
-    const dim3 grid((unsigned)(B * (four ? (H + 3) / 4 : H) * ((W + 63) / 64)), (unsigned)(Co / 16));
-#define RLBM_CONV_FWD(K, R, CC)                                                                                  \
-    do {                                                                                                        \
-        if (relu)                                                                                               \
-            hipLaunchKernelGGL((conv3x3_fwd_kernel<K, true, R, CC>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co); \
-        else                                                                                                    \
-            hipLaunchKernelGGL((conv3x3_fwd_kernel<K, false, R, CC>), grid, dim3(256), 0, s, i, wt, bias, o, H, W, Ci, Co); \
-    } while (0)
-    if (Ci == 16) {
-        if (four)
-            RLBM_CONV_FWD(16, 4, 16);
-        else
-            RLBM_CONV_FWD(16, 1, 16);
-    } else if (Ci == 32) {
-        if (four)
-            RLBM_CONV_FWD(32, 4, 32);
-        else
-            RLBM_CONV_FWD(32, 1, 32);
-    } else if (Ci % 32 == 0) {
-        if (four)
-            RLBM_CONV_FWD(32, 4, 64);
-        else
-            RLBM_CONV_FWD(32, 1, 64);
-    } else {
-        if (four)
-            RLBM_CONV_FWD(16, 4, 64);
-        else
-            RLBM_CONV_FWD(16, 1, 64);
-    }
-#undef RLBM_CONV_FWD
-    return hipGetLastError();
+    ConvInputs x;
+    x.in = in;
+    return conv3x3_forward_ex(x, w, bias, out, B, H, W, Ci, Co, relu, s);
 }
 
 hipError_t conv3x3_adjoint_weights_all(const void *w, void *wt, const AdjointTable &t, hipStream_t s)
