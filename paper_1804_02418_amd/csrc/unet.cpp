@@ -370,12 +370,11 @@ rlbm_status rlbm_unet_forward(rlbm_unet *N, const float *x, float *y, int batch)
         io.pooled = N->pool[level + 1];
         return conv_fwd(N, b, B, &io);
     };
-    auto dec = [&](int a, int b, int up, int skip, int level, int cu) {
+    auto dec = [&](int a, int b, int up, int skip, int cu) {
         ConvInputs io;
         io.in = N->act[up];
         io.skip = N->act[skip];
         io.cu = cu;
-        io.cat = N->cat[level];
         rlbm_status s2 = conv_fwd(N, a, B, &io);
         return s2 ? s2 : conv_fwd(N, b, B);
     };
@@ -384,16 +383,15 @@ rlbm_status rlbm_unet_forward(rlbm_unet *N, const float *x, float *y, int batch)
     if ((st = enc(E3A, E3B, 2))) return st;
     if ((st = enc(E4A, E4B, 3))) return st;
     if ((st = block(BA, BB))) return st;
-    if ((st = dec(D4A, D4B, BB, E4B, 3, c3))) return st;
-    if ((st = dec(D3A, D3B, D4B, E3B, 2, c3))) return st;
-    if ((st = dec(D2A, D2B, D3B, E2B, 1, c2))) return st;
+    if ((st = dec(D4A, D4B, BB, E4B, c3))) return st;
+    if ((st = dec(D3A, D3B, D4B, E3B, c3))) return st;
+    if ((st = dec(D2A, D2B, D3B, E2B, c2))) return st;
     const Layer &h = N->L[HEAD];
     {
         ConvInputs io;
         io.in = N->act[D2B];
         io.skip = N->act[E1B];
         io.cu = c1;
-        io.cat = N->cat[0];
         if ((st = conv_fwd(N, D1A, B, &io))) return st;
         ConvInputs hx;
         hx.head_w = static_cast<const char *>(N->theta_bf) + 2 * h.woff;

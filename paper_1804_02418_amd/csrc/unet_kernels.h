@@ -14,7 +14,6 @@ struct ConvInputs {
     const void *in = nullptr;    // B x H x W x Ci; with skip: B x H/2 x W/2 x cu, upsampled 2x (nearest)
     const void *skip = nullptr;  // with skip, the input is [up(in) | skip], skip B x H x W x (Ci - cu)
     int cu = 0;
-    void *cat = nullptr;         // B x H x W x Ci, where the concatenation is formed when it cannot be read in place
     void *pooled = nullptr;      // also write the 2x2 average of the output, B x H/2 x W/2 x Co
     const void *head_w = nullptr;  // also apply a 1x1 head (BF16 head_o x Co weights, FP32 bias) to the output
     const float *head_b = nullptr;

@@ -950,36 +950,19 @@ hipError_t conv3x3_forward_ex(const ConvInputs &x, const void *w, const float *b
     if (gx > 0x7fffffffLL) return hipErrorInvalidValue;
     const dim3 grid((unsigned)gx, (unsigned)(Co / nb));
 
-    // A concatenation is read in place when its two parts are whole chunks
-    // (and the image halves evenly); otherwise it is formed in x.cat first.
+    // A concatenation is read in place: both parts are multiples of 16
+    // channels, so a chunk width divides both and a chunk lies in one part.
     const bf16 *in = static_cast<const bf16 *>(x.in);
     const bf16 *skip = nullptr;
-    bool cat = false;
-    int cc = 0;
-    for (int c = 128; c >= 16; c /= 2) {
-        if (Ci % c) continue;
-        if (x.skip && (x.cu % c || (Ci - x.cu) % c)) continue;
-        cc = c;
-        break;
-    }
-    if (x.skip) {
+    const bool cat = x.skip != nullptr;
+    if (cat) {
         if (x.cu < 16 || x.cu >= Ci || x.cu % 16 || H % 2 || W % 2) return hipErrorInvalidValue;
-        if (cc) {
-            cat = true;
-            skip = static_cast<const bf16 *>(x.skip);
-            g.cu = x.cu;
-        } else {
-            if (!x.cat) return hipErrorInvalidValue;
-            hipError_t e = up_concat(x.in, x.skip, x.cat, B, H, W, x.cu, Ci - x.cu, s);
-            if (e != hipSuccess) return e;
-            in = static_cast<const bf16 *>(x.cat);
-            for (int c = 128; c >= 16; c /= 2)
-                if (Ci % c == 0) {
-                    cc = c;
-                    break;
-                }
-        }
+        skip = static_cast<const bf16 *>(x.skip);
+        g.cu = x.cu;
     }
+    int cc = 0;
+    for (int c = 128; c >= 16 && !cc; c /= 2)
+        if (Ci % c == 0 && (!cat || (x.cu % c == 0 && (Ci - x.cu) % c == 0))) cc = c;
     // the pooled copy and the head come from the block's output tile when
     // the patch holds whole 2x2 blocks / all output channels
     const bool pool_fused = x.pooled && pr % 2 == 0;

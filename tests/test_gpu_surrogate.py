@@ -122,11 +122,16 @@ def _net_case(seed=3, B=2, H=32, W=32):
     return base, cin, cout, theta, x, t
 
 
-def test_network_forward_and_backward_match_reference():
+@pytest.mark.parametrize("H,W", [(32, 32), (48, 48)])
+def test_network_forward_and_backward_match_reference(H, W):
+    """32 x 32: every pooling, concatenation and the head are fused into the
+    convolutions.  48 x 48: the full-resolution convolutions take one-row
+    patches of 64 pixels, so their pooled copies come from the separate
+    pooling kernel instead."""
     import paper_1804_02418_amd as rl
 
     torch = _torch()
-    base, cin, cout, theta, x, t = _net_case()
+    base, cin, cout, theta, x, t = _net_case(H=H, W=W)
     B, H, W = x.shape[:3]
     net = rl.UNet(base, cin, cout, H, W, max_batch=B)
     net.set_params(theta)
