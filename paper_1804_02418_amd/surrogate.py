@@ -6,7 +6,10 @@ arranges batches and bookkeeping.
 
 * Encoding of a sample (``encode``): an H x W x 16 float32 image with
   channels 0: fluid mask (1), 1: source contact (1 on the bottom row inside
-  its span), 2: drain contact, 3: tau, 4: log10(drive) + 5, 5..15: 0.
+  its span), 2: drain contact, 3: tau, 4: log10(drive) + 5, 5: x / (W - 1),
+  6: y / (H - 1), 7..15: 0.  The coordinates let the network place a pixel
+  in the closed box: under a uniform drive the density settles into a ramp
+  along the drive, which zero padding alone locates poorly.
 * Targets (``targets``): the steady state in linear response, scaled the
   way slow viscous flow scales: ((n - 1)/F, vx (tau - 1/2)/F,
   vy (tau - 1/2)/F), with F the drive magnitude (the velocity of a Stokes
@@ -43,6 +46,8 @@ def encode(w) -> np.ndarray:
             x[0, c["start"]:c["start"] + c["width"], 1 + k] = 1.0
     x[..., 3] = w["tau"]
     x[..., 4] = np.log10(abs(w["F"][0]) + abs(w["F"][1])) + 5.0
+    x[..., 5] = np.linspace(0.0, 1.0, W, dtype=np.float32)[None, :]
+    x[..., 6] = np.linspace(0.0, 1.0, H, dtype=np.float32)[:, None]
     return x
 
 

@@ -1,5 +1,7 @@
 """Host logic of the surrogate warm start (CPU only).
 
+* encode() lays out the sample's description and the pixel coordinates in
+  the network's input channels.
 * decode() rejects a prediction with a non-finite value, a density n <= 0 or
   a speed |v| >= 1 (the sample then starts cold) and scales the others.
 * warm_loop(), the checked solve behind solve_warm(), driven by a scripted
@@ -17,6 +19,19 @@ from paper_1804_02418_amd import surrogate as S
 
 def _sample(F=1e-5, tau=0.8):
     return dict(nx=4, ny=3, tau=tau, F=(F, 0.0), contacts=[], init=dict(n=1.0, T=1.0, vx=0.0, vy=0.0))
+
+
+def test_encode_channels():
+    w = dict(nx=5, ny=3, tau=0.9, F=(1e-5, 0.0),
+             contacts=[dict(edge="bottom", start=1, width=2), dict(edge="bottom", start=3, width=1)])
+    x = S.encode(w)
+    assert x.shape == (3, 5, S.CIN) and x.dtype == np.float32
+    assert np.all(x[..., 0] == 1) and np.all(x[..., 3] == np.float32(0.9))
+    assert np.allclose(x[..., 4], 0.0, atol=1e-6)  # log10(1e-5) + 5
+    assert list(np.flatnonzero(x[0, :, 1])) == [1, 2] and list(np.flatnonzero(x[0, :, 2])) == [3]
+    assert not x[1:, :, 1:3].any()
+    assert np.allclose(x[1, :, 5], [0, 0.25, 0.5, 0.75, 1]) and np.allclose(x[:, 2, 6], [0, 0.5, 1])
+    assert not x[..., 7:].any()
 
 
 def test_decode_scales_and_rejects():
