@@ -342,13 +342,19 @@ __global__ void conv3x3_adjoint_all_kernel(const bf16 *__restrict__ w, bf16 *__r
 // The matrix instructions want 8 consecutive pixels of one channel per
 // lane, while NHWC keeps channels contiguous, so each row segment of SEG
 // input pixels is staged through LDS transposed: the CIB input channels of
-// the rows y-1, y, y+1 once, Bs[row][ci][k], and the 16 output channels in
-// three copies shifted by the tap's dx, As[dx][co][k] (a 16-channel tile is
+// the rows y-1, y, y+1, Bs[row][ci][k], and the 16 output channels in three
+// copies shifted by the tap's dx, As[dx][co][k] (a 16-channel tile is
 // cheaper to replicate than CIB channels), so that every operand is one
-// aligned 16-byte LDS read.  CIB * SEG = 2048 (64 x 32, 32 x 64 or 16 x 128,
-// by the input channel count): the four wavefronts take CIB / 16 channel
-// tiles times SEG / 32 pixel quarters, each keeps the 9 taps' 16 x 16
-// accumulators, and the quarters of a tile are added in order at the end.
+// aligned 16-byte LDS read.  A lane stages a pair of adjacent pixels: it
+// loads both pixels' 8 channels (16-byte raw buffer loads; an offset past
+// the buffer's end reads zero, which pads the image) and writes each
+// channel's pair as one 32-bit word, consecutive lanes taking consecutive
+// pairs of one row.  The loads of the next (row, segment) are in flight
+// while the matrix instructions consume the current one.  CIB * SEG = 2048
+// (64 x 32, 32 x 64 or 16 x 128, by the input channel count): the four
+// wavefronts take CIB / 16 channel tiles times SEG / 32 pixel quarters,
+// each keeps the 9 taps' 16 x 16 accumulators, and the quarters of a tile
+// are added in order at the end.
 // grid.x = chunks (whole rows each), grid.y = (Co / 16) * ceil(Ci / CIB).
 template <int CIB>
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restrict__ dpre,
@@ -356,14 +362,21 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
                                                             int B, int H, int W, int Ci, int Co, int rows_per_chunk)
 {
     constexpr int SEG = 2048 / CIB, NCT = CIB / 16;
+    constexpr int SP = SEG + 8;            // staged row of one channel: 16-byte aligned, padded
+    constexpr int NP = SEG / 2;            // pixel pairs of a segment
+    constexpr int G = CIB / 8;             // 16-byte groups of a pixel's CIB channels
+    constexpr int XN = 3 * NP * G;         // input units: (row, group, pair)
+    constexpr int XU = (XN + 255) / 256;
+    constexpr int DN = 2 * NP;             // output-gradient units: (group of 8 channels, pair)
+    constexpr int DU = (DN + 255) / 256;
     // staging (As then Bs) and, at the end, the reduction of the four waves'
     // accumulators share one LDS buffer
-    constexpr int kAs = 3 * 16 * SEG, kBs = 3 * CIB * SEG;
+    constexpr int kAs = 3 * 16 * SP, kBs = 3 * CIB * SP;
     constexpr int kRed = 4 * 9 * 4 * 64 * (int)sizeof(float);
     constexpr int kBytes = (kAs + kBs) * (int)sizeof(bf16) > kRed ? (kAs + kBs) * (int)sizeof(bf16) : kRed;
     __shared__ __attribute__((aligned(16))) char smem[kBytes];
-    bf16 (*As)[16][SEG] = reinterpret_cast<bf16 (*)[16][SEG]>(smem);
-    bf16 (*Bs)[CIB][SEG] = reinterpret_cast<bf16 (*)[CIB][SEG]>(smem + kAs * sizeof(bf16));
+    bf16 *const As = reinterpret_cast<bf16 *>(smem);  // [3][16][SP]
+    bf16 *const Bs = As + kAs;                         // [3][CIB][SP]
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int ct = wave % NCT, kp = wave / NCT;
     const int cib = (Ci + CIB - 1) / CIB;
@@ -373,65 +386,121 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
     const int r = lane & 15, kq = lane >> 4;
     const long long row0 = (long long)blockIdx.x * rows_per_chunk;
     const long long rows_end = row0 + rows_per_chunk < (long long)B * H ? row0 + rows_per_chunk : (long long)B * H;
+    const int nseg = (W + SEG - 1) / SEG;
+    const int nit = rows_end > row0 ? (int)(rows_end - row0) * nseg : 0;  // (row, segment) iterations
+    constexpr unsigned kOut = 0x80000000u;
+    const __amdgpu_buffer_rsrc_t xrs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)in, (short)0, B * H * W * Ci * 2, 0x00020000);
+    const __amdgpu_buffer_rsrc_t drs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)dpre, (short)0, B * H * W * Co * 2, 0x00020000);
+    // each unit's fixed part of its address, and whether it reads anything
+    int xj[XU], xrow[XU], xc[XU], dj[DU], dc[DU];
+    bool xv[XU], dvld[DU];
+#pragma unroll
+    for (int i = 0; i < XU; ++i) {
+        const int u = t + 256 * i;
+        const int j = u % NP, rest = u / NP, g = rest % G, rr = rest / G;
+        xj[i] = 2 * j;
+        xrow[i] = rr - 1;
+        xc[i] = ci0 + 8 * g;
+        xv[i] = (XN % 256 == 0 || u < XN) & (ci0 + 8 * g < Ci);
+    }
+#pragma unroll
+    for (int i = 0; i < DU; ++i) {
+        const int u = t + 256 * i;
+        dj[i] = 2 * (u % NP) - 1;
+        dc[i] = co0 + 8 * (u / NP);
+        dvld[i] = DN % 256 == 0 || u < DN;
+    }
+    bf16x8 xa[XU], xb[XU], dv[DU][4];
+    auto load = [&](int it) {
+        const long long gr = row0 + it / nseg;
+        const int x0 = (it % nseg) * SEG, y = (int)(gr % H), img = (int)(gr / H);
+#pragma unroll
+        for (int i = 0; i < XU; ++i) {
+            const int yy = y + xrow[i], xx = x0 + xj[i];
+            const bool ok = xv[i] & ((unsigned)yy < (unsigned)H);
+            const unsigned o = (unsigned)((((img * H + yy) * W + xx) * Ci + xc[i]) * 2);
+            const unsigned o0 = ok & (xx < W) ? o : kOut, o1 = ok & (xx + 1 < W) ? o + 2u * Ci : kOut;
+            xa[i] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(xrs, (int)o0, 0, 0));
+            xb[i] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(xrs, (int)o1, 0, 0));
+        }
+#pragma unroll
+        for (int i = 0; i < DU; ++i) {
+            const int xs = x0 + dj[i];  // input pixels xs .. xs + 3
+            const unsigned o = (unsigned)((((img * H + y) * W + xs) * Co + dc[i]) * 2);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const bool ok = dvld[i] & ((unsigned)(xs + q) < (unsigned)W);
+                dv[i][q] = __builtin_bit_cast(
+                    bf16x8, __builtin_amdgcn_raw_buffer_load_b128(drs, (int)(ok ? o + 2u * Co * q : kOut), 0, 0));
+            }
+        }
+    };
+    auto pack = [](bf16 lo, bf16 hi) {
+        return (unsigned)__builtin_bit_cast(unsigned short, lo) | ((unsigned)__builtin_bit_cast(unsigned short, hi) << 16);
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int i = 0; i < XU; ++i) {
+            const int u = t + 256 * i;
+            if (XN % 256 == 0 || u < XN) {
+                const int j = u % NP, rest = u / NP, g = rest % G, rr = rest / G;
+                bf16 *const p = Bs + (rr * CIB + 8 * g) * SP + 2 * j;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) *reinterpret_cast<unsigned *>(p + e * SP) = pack(xa[i][e], xb[i][e]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < DU; ++i) {
+            const int u = t + 256 * i;
+            if (DN % 256 == 0 || u < DN) {
+                const int j = u % NP, g = u / NP;
+                // As[dx][co][k] = dpre[x0 + k + 1 - dx][co]: for k = 2j, 2j + 1 the
+                // pixels x0 + 2j + 1 - dx and x0 + 2j + 2 - dx, i.e. dv[2 - dx], dv[3 - dx]
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    bf16 *const p = As + (dx * 16 + 8 * g) * SP + 2 * j;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        *reinterpret_cast<unsigned *>(p + e * SP) = pack(dv[i][2 - dx][e], dv[i][3 - dx][e]);
+                }
+            }
+        }
+    };
     f32x4 acc[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16 z = (bf16)0.f;
-    for (long long gr = row0; gr < rows_end; ++gr) {
-        const int y = (int)(gr % H);
-        const long long img = gr / H;
-        for (int x0 = 0; x0 < W; x0 += SEG) {
-            const int seg = W - x0 < SEG ? W - x0 : SEG;
-            // ---- stage dpre: pixels x0-1 .. x0+SEG, 16 channels, two per
-            // unit; pixel x0 + u serves shift dx at k = u - 1 + dx
-            for (int unit = t; unit < (SEG + 2) * 8; unit += 256) {
-                const int u = unit / 8 - 1, cp = (unit % 8) * 2;
-                const int xx = x0 + u;
-                bf16 v0 = z, v1 = z;
-                if ((unsigned)xx < (unsigned)W) {
-                    const bf16 *q = dpre + ((img * H + y) * W + xx) * Co + co0 + cp;
-                    v0 = q[0];
-                    v1 = q[1];
-                }
+    // no branch around the products: pixels past the image and channels past
+    // Ci were staged as zeros, so an idle quarter or tile adds zero (and an
+    // inactive tile's sums are not written)
+    auto compute = [&]() {
+        bf16x8 a[3];
 #pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
-                    const int k = u - 1 + dx;
-                    if (k >= 0 && k < SEG) {
-                        As[dx][cp][k] = v0;
-                        As[dx][cp + 1][k] = v1;
-                    }
-                }
-            }
-            // ---- stage in: rows y-1..y+1, pixels x0 .. x0+SEG-1, CIB channels
-            // in groups of 8
-            for (int unit = t; unit < 3 * SEG * (CIB / 8); unit += 256) {
-                const int g = unit % (CIB / 8), rest = unit / (CIB / 8);
-                const int k = rest % SEG, rr = rest / SEG;
-                const int yy = y + rr - 1, xx = x0 + k, c = ci0 + 8 * g;
-                bf16x8 v;
-                if ((unsigned)yy < (unsigned)H && xx < W && c < Ci)
-                    v = *reinterpret_cast<const bf16x8 *>(in + ((img * H + yy) * W + xx) * Ci + c);
-                else
-                    for (int e = 0; e < 8; ++e) v[e] = z;
+        for (int dx = 0; dx < 3; ++dx) a[dx] = *reinterpret_cast<const bf16x8 *>(&As[(dx * 16 + r) * SP + kp * 32 + kq * 8]);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) Bs[rr][8 * g + e][k] = v[e];
-            }
+        for (int dy = 0; dy < 3; ++dy) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[(dy * CIB + 16 * ct + r) * SP + kp * 32 + kq * 8]);
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+                acc[dy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[dx], b, acc[dy * 3 + dx], 0, 0, 0);
+        }
+    };
+    if (nit > 0) {
+        load(0);
+        stage();
+        __syncthreads();
+        for (int it = 0; it + 1 < nit; ++it) {
+            load(it + 1);  // in flight while this iteration's products run
+            __builtin_amdgcn_sched_barrier(0);
+            compute();
             __syncthreads();
-            if (active && kp * 32 < seg) {
-                bf16x8 a[3];
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx) a[dx] = *reinterpret_cast<const bf16x8 *>(&As[dx][r][kp * 32 + kq * 8]);
-#pragma unroll
-                for (int dy = 0; dy < 3; ++dy) {
-                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[dy][16 * ct + r][kp * 32 + kq * 8]);
-#pragma unroll
-                    for (int dx = 0; dx < 3; ++dx)
-                        acc[dy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[dx], b, acc[dy * 3 + dx], 0, 0, 0);
-                }
-            }
+            stage();
             __syncthreads();
         }
+        compute();
     }
+    __syncthreads();  // the staging LDS becomes the reduction buffer
     // add the pixel quarters of each channel tile in order, through LDS
     float *red = reinterpret_cast<float *>(smem);  // 4 x 9 x 4 x 64 floats
 #pragma unroll
@@ -1044,6 +1113,8 @@ hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part
                                    int Ci, int Co, hipStream_t s)
 {
     if (Ci % 16 || Co % 16 || B < 1 || H < 1 || W < 1) return hipErrorInvalidValue;
+    // both tensors are addressed with 32-bit byte offsets (buffer loads)
+    if ((long long)B * H * W * (Ci > Co ? Ci : Co) * 2 >= (1LL << 31)) return hipErrorInvalidValue;
     const int chunks = conv3x3_wgrad_chunks(B, H, W, Ci, Co);
     const int per = (int)(((long long)B * H + chunks - 1) / chunks);
     const int cib = wgrad_cib(Ci);
