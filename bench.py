@@ -401,6 +401,19 @@ def batch_throughput(storage: str = "f32", count: int = 256, steps: int = 100, w
     out["default_shape_no_graph"] = entry(timed(default, False))
     tuned = rl.Batch(samples, storage, stream=stream.cuda_stream)
     tuned.autotune(20)
+
+    def tiles_by_class(B):
+        """Tile shapes in use per width class (multiple of 256, of 128 only, other)."""
+        out = {}
+        for w, L in zip(samples, B.lattices):
+            k = "w%256==0" if w["nx"] % 256 == 0 else "w%128==0" if w["nx"] % 128 == 0 else "other"
+            t, r = L.launch_shape()
+            out.setdefault(k, {}).setdefault(f"{t}x{r}", 0)
+            out[k][f"{t}x{r}"] += 1
+        return out
+
+    out["tiles_default"] = tiles_by_class(default)
+    out["tiles_autotuned"] = tiles_by_class(tuned)
     t_default, t_tuned = [], []
     for _ in range(rounds):
         t_default.append(timed(default, True))

@@ -234,6 +234,10 @@ rlbm_status rlbm_set_state(rlbm_lattice *lat, const void *src, size_t bytes);
  * computed independently); only speed does.  Default: the largest of
  * 64/128/256 not above the width rounded up to 64. */
 rlbm_status rlbm_set_launch_shape(rlbm_lattice *lat, int tile_x, int rows);
+/* The lattice's current work decomposition (set, defaulted or chosen by an
+ * autotuner, also for a sample of a batch); *tile_x, *rows: caller-owned,
+ * either may be NULL. */
+rlbm_status rlbm_get_launch_shape(rlbm_lattice *lat, int *tile_x, int *rows);
 
 /* Block order of the step kernel: xcd_contiguous = 1 deals each of the 8
  * XCDs (with its own L2) one contiguous range of the launch's blocks, so
@@ -326,12 +330,16 @@ rlbm_status rlbm_batch_residual(rlbm_batch *b, double *r);
 rlbm_status rlbm_batch_step_until(rlbm_batch *b, int64_t max_steps, int64_t check_every, double tol,
                                   int64_t *steps, double *r);
 
-/* Autotuner for the batch: time the batched step with the samples' shapes
- * and store forms as they are, then with every sample's tile width set to
- * each candidate (64, 128, 256, capped at the sample's interior width), with
- * ordinary and with streaming stores; keep the fastest (the entry setting
- * unless a candidate is more than 1% faster), restore all states.  ms_per_step: NULL or 6
- * entries, the candidates' times in that order. */
+/* Autotuner for the batch, in two stages, every time the faster of two runs
+ * of trial_steps steps.  Stage 1: the samples' shapes and store forms as
+ * they are, then every sample's tile width set to each candidate (64, 128,
+ * 256, capped at the sample's width) with ordinary and with streaming
+ * stores; the entry setting is kept unless a candidate is more than 1%
+ * faster.  Stage 2: per width class (widths that are multiples of 256, of
+ * 128 only, or neither), each tile width that divides the class's widths,
+ * the other classes held at their best; a change is kept when more than 1%
+ * faster.  Restores every sample's state and keeps the fastest setting.
+ * ms_per_step: NULL or 6 entries, stage 1's candidates in that order. */
 rlbm_status rlbm_batch_autotune(rlbm_batch *b, int trial_steps, double *ms_per_step);
 
 /* Item order of the batched kernel, as rlbm_set_block_order: 1 deals each

@@ -50,6 +50,7 @@ _lib = None
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64 = ctypes.c_int64
+_ip = ctypes.POINTER(ctypes.c_int)
 
 # name -> (argtypes, restype); restype None = rlbm_status (int)
 SIGNATURES = {
@@ -88,6 +89,7 @@ SIGNATURES = {
     "rlbm_get_state": ([_vp, _vp, ctypes.c_size_t], None),
     "rlbm_set_state": ([_vp, _vp, ctypes.c_size_t], None),
     "rlbm_set_launch_shape": ([_vp, ctypes.c_int, ctypes.c_int], None),
+    "rlbm_get_launch_shape": ([_vp, _ip, _ip], None),
     "rlbm_autotune": ([_vp, ctypes.c_int, _dp], None),
     "rlbm_set_streaming_stores": ([_vp, ctypes.c_int], None),
     "rlbm_synchronize": ([_vp], None),
@@ -329,6 +331,12 @@ class Lattice:
 
     def set_launch_shape(self, tile_x: int, rows: int):
         check(lib().rlbm_set_launch_shape(self._h, int(tile_x), int(rows)))
+
+    def launch_shape(self):
+        """(tile_x, rows) of the step's work decomposition."""
+        t, r = ctypes.c_int(), ctypes.c_int()
+        check(lib().rlbm_get_launch_shape(self._h, ctypes.byref(t), ctypes.byref(r)))
+        return t.value, r.value
 
     def set_streaming_stores(self, on: bool):
         check(lib().rlbm_set_streaming_stores(self._h, int(bool(on))))

@@ -924,6 +924,14 @@ rlbm_status rlbm_set_launch_shape(rlbm_lattice *L, int tile_x, int rows)
     return RLBM_OK;
 }
 
+rlbm_status rlbm_get_launch_shape(rlbm_lattice *L, int *tile_x, int *rows)
+{
+    CHECK_L(L);
+    if (tile_x) *tile_x = L->shape.tile_x;
+    if (rows) *rows = L->shape.rows;
+    return RLBM_OK;
+}
+
 rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
 {
     CHECK_L(L);
@@ -1428,39 +1436,93 @@ rlbm_status rlbm_batch_autotune(rlbm_batch *B, int trial_steps, double *ms_per_s
     std::vector<LaunchShape> shape0(n);
     for (int s = 0; s < n; ++s) shape0[s] = B->lat[s]->shape;
     const int tiles[3] = {64, 128, 256};
-    double best = INFINITY;
-    int best_c = -1;  // -1: the shapes and store forms the samples had on entry
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     rlbm_status st = RLBM_OK;
     std::vector<int> nt0(n);
     for (int s = 0; s < n; ++s) nt0[s] = B->lat[s]->nt_store;
+    // ms per step of the current setting: the faster of two timed runs
+    // (each after two untimed steps), so that one slow run does not decide
+    auto trial = [&](double &per) {
+        per = INFINITY;
+        for (int rep = 0; rep < 2 && st == RLBM_OK; ++rep) {
+            st = rlbm_batch_step(B, 2, 0);
+            if (st) break;
+            (void)hipEventRecord(e0, B->stream);
+            st = rlbm_batch_step(B, trial_steps, 0);
+            if (st) break;
+            (void)hipEventRecord(e1, B->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            per = std::min(per, (double)ms / trial_steps);
+        }
+    };
+    auto capped = [](int t, int w) {
+        while (t > 64 && t / 2 >= w) t /= 2;
+        return t;
+    };
+    // stage 1: one tile width (capped at each sample's width) and store form
+    // for every sample; the entry setting is left only for a candidate more
+    // than 1% faster
+    double best = INFINITY;
+    int best_c = -1;  // -1: the shapes and store forms the samples had on entry
     for (int c = -1; c < 6 && st == RLBM_OK; ++c) {
         if (c >= 0) {
             for (int s = 0; s < n; ++s) {
-                const int w = B->lat[s]->nx;
-                int t = tiles[c % 3];
-                while (t > 64 && t / 2 >= w) t /= 2;
-                B->lat[s]->shape = LaunchShape{t, 256 / t};
+                B->lat[s]->shape = LaunchShape{capped(tiles[c % 3], B->lat[s]->nx), 256 / capped(tiles[c % 3], B->lat[s]->nx)};
                 rlbm_set_streaming_stores(B->lat[s], c / 3);
             }
         }
-        st = rlbm_batch_step(B, 2, 0);
+        double per = INFINITY;
+        trial(per);
         if (st) break;
-        (void)hipEventRecord(e0, B->stream);
-        st = rlbm_batch_step(B, trial_steps, 0);
-        if (st) break;
-        (void)hipEventRecord(e1, B->stream);
-        (void)hipEventSynchronize(e1);
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const double per = ms / trial_steps;
         if (ms_per_step && c >= 0) ms_per_step[c] = per;
-        // leaving the entry setting takes a margin above the trials' noise
         if (per < (best_c == -1 ? 0.99 * best : best)) {
             best = per;
             best_c = c;
+        }
+    }
+    std::vector<LaunchShape> shape1(n);
+    std::vector<int> nt1(n);
+    for (int s = 0; s < n; ++s) {
+        if (best_c >= 0) {
+            const int t = capped(tiles[best_c % 3], B->lat[s]->nx);
+            shape1[s] = LaunchShape{t, 256 / t};
+            nt1[s] = best_c / 3;
+        } else {
+            shape1[s] = shape0[s];
+            nt1[s] = nt0[s];
+        }
+    }
+    // stage 2: per width class (a multiple of 256; of 128 only; anything
+    // else), each width that tiles the class's rows exactly, the other
+    // classes held at their best; a change needs more than 1% to be kept
+    auto cls = [](int w) { return w % 256 == 0 ? 0 : w % 128 == 0 ? 1 : 2; };
+    for (int k = 0; k < 3 && st == RLBM_OK; ++k) {
+        bool present = false;
+        for (int s = 0; s < n; ++s) present = present || cls(B->lat[s]->nx) == k;
+        if (!present) continue;
+        for (int ti = 0; ti < 3 && st == RLBM_OK; ++ti) {
+            const int t = tiles[ti];
+            if ((k == 1 && t == 256) || (k == 2 && t != 64)) continue;
+            bool same = true;
+            for (int s = 0; s < n; ++s) {
+                const bool mine = cls(B->lat[s]->nx) == k;
+                const int ts = mine ? capped(t, B->lat[s]->nx) : shape1[s].tile_x;
+                same = same && (!mine || ts == shape1[s].tile_x);
+                B->lat[s]->shape = mine ? LaunchShape{ts, 256 / ts} : shape1[s];
+                rlbm_set_streaming_stores(B->lat[s], nt1[s]);
+            }
+            if (same) continue;
+            double per = INFINITY;
+            trial(per);
+            if (st) break;
+            if (per < 0.99 * best) {
+                best = per;
+                for (int s = 0; s < n; ++s) shape1[s] = B->lat[s]->shape;
+            }
         }
     }
     (void)hipEventDestroy(e0);
@@ -1476,16 +1538,8 @@ rlbm_status rlbm_batch_autotune(rlbm_batch *B, int trial_steps, double *ms_per_s
         if (e == hipSuccess)
             e = hipMemcpyAsync(L->prev, save + off[s] + pb + 4 * P * 8, 2 * P * 8, hipMemcpyDeviceToDevice, B->stream);
         if (e != hipSuccess && !st) st = fail(RLBM_EDEVICE, "rlbm_batch_autotune: restore: %s", hipGetErrorString(e));
-        if (best_c >= 0) {
-            const int w = L->nx;
-            int t = tiles[best_c % 3];
-            while (t > 64 && t / 2 >= w) t /= 2;
-            L->shape = LaunchShape{t, 256 / t};
-            rlbm_set_streaming_stores(L, best_c / 3);
-        } else {
-            L->shape = shape0[s];
-            rlbm_set_streaming_stores(L, nt0[s]);
-        }
+        L->shape = st ? shape0[s] : shape1[s];
+        rlbm_set_streaming_stores(L, st ? nt0[s] : nt1[s]);
     }
     {
         hipError_t e = hipStreamSynchronize(B->stream);

@@ -94,8 +94,12 @@ def test_batch_autotune_restores_state():
     B.step(4)
     snap = [bl.read_populations() for bl in B.lattices]
     ms = B.autotune(3)
-    print("batch autotune ms/step", ms, flush=True)
+    print("batch autotune ms/step", ms, [bl.launch_shape() for bl in B.lattices], flush=True)
     assert (ms > 0).all()
+    # the chosen decomposition is a valid one for every sample
+    for bl in B.lattices:
+        t, r = bl.launch_shape()
+        assert t in (64, 128, 256) and t * r == 256
     for k, bl in enumerate(B.lattices):
         assert bl.time == 4 and np.array_equal(bl.read_populations(), snap[k])
     B.step(6)
