@@ -339,44 +339,46 @@ __global__ void conv3x3_adjoint_all_kernel(const bf16 *__restrict__ w, bf16 *__r
 // taken over the input pixel x' = x + dx - 1 of a row:
 //   sum_x' dpre[y][x' + 1 - dx][co] * in[y + dy - 1][x'][ci]
 // (the terms dropped or added at the image edges are zero on either side).
-// The matrix instructions want 8 consecutive pixels of one channel per
-// lane, while NHWC keeps channels contiguous, so each row segment of SEG
-// input pixels is staged through LDS transposed: the CIB input channels of
-// the rows y-1, y, y+1, Bs[row][ci][k], and the 16 output channels in three
-// copies shifted by the tap's dx, As[dx][co][k] (a 16-channel tile is
-// cheaper to replicate than CIB channels), so that every operand is one
-// aligned 16-byte LDS read.  A lane stages a pair of adjacent pixels: it
-// loads both pixels' 8 channels (16-byte raw buffer loads; an offset past
-// the buffer's end reads zero, which pads the image) and writes each
-// channel's pair as one 32-bit word, consecutive lanes taking consecutive
-// pairs of one row.  The loads of the next (row, segment) are in flight
-// while the matrix instructions consume the current one.  CIB * SEG = 2048
-// (64 x 32, 32 x 64 or 16 x 128, by the input channel count): the four
-// wavefronts take CIB / 16 channel tiles times SEG / 32 pixel quarters,
-// each keeps the 9 taps' 16 x 16 accumulators, and the quarters of a tile
-// are added in order at the end.
-// grid.x = chunks (whole rows each), grid.y = (Co / 16) * ceil(Ci / CIB).
-template <int CIB>
+// A chunk is `per` consecutive rows of one image (chunk c: image c / cpi,
+// rows from (c % cpi) * per), taken RB rows and one segment of SEG pixels
+// at a time.  The matrix instructions want 8 consecutive pixels of one
+// channel per lane, while NHWC keeps channels contiguous, so each segment
+// is staged through LDS transposed: the CIB input channels of the RB + 2
+// rows y-1 .. y+RB, Bs[row][ci][k], and for each of the RB rows the 16
+// output channels in three copies shifted by the tap's dx, As[row][dx][co][k]
+// (a 16-channel tile is cheaper to replicate than CIB channels), so that
+// every operand is one aligned 16-byte LDS read.  A lane stages a pair of
+// adjacent pixels: it loads both pixels' 8 channels (16-byte raw buffer
+// loads; an offset past the buffer's end reads zero, which pads the image
+// and the rows past the chunk) and writes each channel's pair as one 32-bit
+// word, consecutive lanes taking consecutive pairs of one row.  The loads of
+// the next step are in flight while the matrix instructions consume the
+// current one.  CIB * SEG = 2048 (64 x 32, 32 x 64 or 16 x 128, by the input
+// channel count): the four wavefronts take CIB / 16 channel tiles times
+// SEG / 32 pixel quarters, each keeps the 9 taps' 16 x 16 accumulators over
+// all its rows, and the quarters of a tile are added in order at the end.
+// grid.x = chunks = B * cpi, grid.y = (Co / 16) * ceil(Ci / CIB).
+template <int CIB, int RB>
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restrict__ dpre,
                                                             const bf16 *__restrict__ in, float *__restrict__ part,
-                                                            int B, int H, int W, int Ci, int Co, int rows_per_chunk)
+                                                            int B, int H, int W, int Ci, int Co, int cpi, int per)
 {
     constexpr int SEG = 2048 / CIB, NCT = CIB / 16;
     constexpr int SP = SEG + 8;            // staged row of one channel: 16-byte aligned, padded
     constexpr int NP = SEG / 2;            // pixel pairs of a segment
     constexpr int G = CIB / 8;             // 16-byte groups of a pixel's CIB channels
-    constexpr int XN = 3 * NP * G;         // input units: (row, group, pair)
+    constexpr int XN = (RB + 2) * NP * G;  // input units: (row, group, pair)
     constexpr int XU = (XN + 255) / 256;
-    constexpr int DN = 2 * NP;             // output-gradient units: (group of 8 channels, pair)
+    constexpr int DN = RB * 2 * NP;        // output-gradient units: (row, group of 8 channels, pair)
     constexpr int DU = (DN + 255) / 256;
     // staging (As then Bs) and, at the end, the reduction of the four waves'
     // accumulators share one LDS buffer
-    constexpr int kAs = 3 * 16 * SP, kBs = 3 * CIB * SP;
+    constexpr int kAs = RB * 3 * 16 * SP, kBs = (RB + 2) * CIB * SP;
     constexpr int kRed = 4 * 9 * 4 * 64 * (int)sizeof(float);
     constexpr int kBytes = (kAs + kBs) * (int)sizeof(bf16) > kRed ? (kAs + kBs) * (int)sizeof(bf16) : kRed;
     __shared__ __attribute__((aligned(16))) char smem[kBytes];
-    bf16 *const As = reinterpret_cast<bf16 *>(smem);  // [3][16][SP]
-    bf16 *const Bs = As + kAs;                         // [3][CIB][SP]
+    bf16 *const As = reinterpret_cast<bf16 *>(smem);  // [RB][3][16][SP]
+    bf16 *const Bs = As + kAs;                         // [RB + 2][CIB][SP]
     const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
     const int ct = wave % NCT, kp = wave / NCT;
     const int cib = (Ci + CIB - 1) / CIB;
@@ -384,17 +386,17 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
     const int co0 = og * 16, ci0 = cb * CIB;
     const bool active = ci0 + 16 * ct < Ci;
     const int r = lane & 15, kq = lane >> 4;
-    const long long row0 = (long long)blockIdx.x * rows_per_chunk;
-    const long long rows_end = row0 + rows_per_chunk < (long long)B * H ? row0 + rows_per_chunk : (long long)B * H;
+    const int img = (int)blockIdx.x / cpi;
+    const int y0 = ((int)blockIdx.x % cpi) * per, y1 = y0 + per < H ? y0 + per : H;
     const int nseg = (W + SEG - 1) / SEG;
-    const int nit = rows_end > row0 ? (int)(rows_end - row0) * nseg : 0;  // (row, segment) iterations
+    const int nit = y1 > y0 ? (y1 - y0 + RB - 1) / RB * nseg : 0;  // (row group, segment) steps
     constexpr unsigned kOut = 0x80000000u;
     const __amdgpu_buffer_rsrc_t xrs =
         __builtin_amdgcn_make_buffer_rsrc((void *)in, (short)0, B * H * W * Ci * 2, 0x00020000);
     const __amdgpu_buffer_rsrc_t drs =
         __builtin_amdgcn_make_buffer_rsrc((void *)dpre, (short)0, B * H * W * Co * 2, 0x00020000);
     // each unit's fixed part of its address, and whether it reads anything
-    int xj[XU], xrow[XU], xc[XU], dj[DU], dc[DU];
+    int xj[XU], xrow[XU], xc[XU], dj[DU], drow[DU], dc[DU];
     bool xv[XU], dvld[DU];
 #pragma unroll
     for (int i = 0; i < XU; ++i) {
@@ -408,17 +410,18 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
 #pragma unroll
     for (int i = 0; i < DU; ++i) {
         const int u = t + 256 * i;
-        dj[i] = 2 * (u % NP) - 1;
-        dc[i] = co0 + 8 * (u / NP);
+        const int j = u % NP, rest = u / NP;
+        dj[i] = 2 * j - 1;
+        dc[i] = co0 + 8 * (rest % 2);
+        drow[i] = rest / 2;
         dvld[i] = DN % 256 == 0 || u < DN;
     }
     bf16x8 xa[XU], xb[XU], dv[DU][4];
     auto load = [&](int it) {
-        const long long gr = row0 + it / nseg;
-        const int x0 = (it % nseg) * SEG, y = (int)(gr % H), img = (int)(gr / H);
+        const int yg = y0 + (it / nseg) * RB, x0 = (it % nseg) * SEG;
 #pragma unroll
         for (int i = 0; i < XU; ++i) {
-            const int yy = y + xrow[i], xx = x0 + xj[i];
+            const int yy = yg + xrow[i], xx = x0 + xj[i];
             const bool ok = xv[i] & ((unsigned)yy < (unsigned)H);
             const unsigned o = (unsigned)((((img * H + yy) * W + xx) * Ci + xc[i]) * 2);
             const unsigned o0 = ok & (xx < W) ? o : kOut, o1 = ok & (xx + 1 < W) ? o + 2u * Ci : kOut;
@@ -427,11 +430,12 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
         }
 #pragma unroll
         for (int i = 0; i < DU; ++i) {
-            const int xs = x0 + dj[i];  // input pixels xs .. xs + 3
+            const int y = yg + drow[i], xs = x0 + dj[i];  // input pixels xs .. xs + 3 of a row of the chunk
             const unsigned o = (unsigned)((((img * H + y) * W + xs) * Co + dc[i]) * 2);
+            const bool rok = dvld[i] & (y < y1);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const bool ok = dvld[i] & ((unsigned)(xs + q) < (unsigned)W);
+                const bool ok = rok & ((unsigned)(xs + q) < (unsigned)W);
                 dv[i][q] = __builtin_bit_cast(
                     bf16x8, __builtin_amdgcn_raw_buffer_load_b128(drs, (int)(ok ? o + 2u * Co * q : kOut), 0, 0));
             }
@@ -455,12 +459,12 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
         for (int i = 0; i < DU; ++i) {
             const int u = t + 256 * i;
             if (DN % 256 == 0 || u < DN) {
-                const int j = u % NP, g = u / NP;
-                // As[dx][co][k] = dpre[x0 + k + 1 - dx][co]: for k = 2j, 2j + 1 the
-                // pixels x0 + 2j + 1 - dx and x0 + 2j + 2 - dx, i.e. dv[2 - dx], dv[3 - dx]
+                const int j = u % NP, rest = u / NP, g = rest % 2, rb = rest / 2;
+                // As[rb][dx][co][k] = dpre[row rb][x0 + k + 1 - dx][co]: for k = 2j, 2j + 1
+                // the pixels x0 + 2j + 1 - dx and x0 + 2j + 2 - dx, i.e. dv[2 - dx], dv[3 - dx]
 #pragma unroll
                 for (int dx = 0; dx < 3; ++dx) {
-                    bf16 *const p = As + (dx * 16 + 8 * g) * SP + 2 * j;
+                    bf16 *const p = As + ((rb * 3 + dx) * 16 + 8 * g) * SP + 2 * j;
 #pragma unroll
                     for (int e = 0; e < 8; ++e)
                         *reinterpret_cast<unsigned *>(p + e * SP) = pack(dv[i][2 - dx][e], dv[i][3 - dx][e]);
@@ -471,19 +475,24 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
     f32x4 acc[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // no branch around the products: pixels past the image and channels past
-    // Ci were staged as zeros, so an idle quarter or tile adds zero (and an
-    // inactive tile's sums are not written)
+    // no branch around the products: pixels past the image, rows past the
+    // chunk and channels past Ci were staged as zeros, so an idle quarter,
+    // row or tile adds zero (and an inactive tile's sums are not written)
     auto compute = [&]() {
-        bf16x8 a[3];
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) a[dx] = *reinterpret_cast<const bf16x8 *>(&As[(dx * 16 + r) * SP + kp * 32 + kq * 8]);
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Bs[(dy * CIB + 16 * ct + r) * SP + kp * 32 + kq * 8]);
+        for (int rb = 0; rb < RB; ++rb) {
+            bf16x8 a[3];
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx)
-                acc[dy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[dx], b, acc[dy * 3 + dx], 0, 0, 0);
+                a[dx] = *reinterpret_cast<const bf16x8 *>(&As[((rb * 3 + dx) * 16 + r) * SP + kp * 32 + kq * 8]);
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) {
+                const bf16x8 b =
+                    *reinterpret_cast<const bf16x8 *>(&Bs[((rb + dy) * CIB + 16 * ct + r) * SP + kp * 32 + kq * 8]);
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+                    acc[dy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[dx], b, acc[dy * 3 + dx], 0, 0, 0);
+            }
         }
     };
     if (nit > 0) {
@@ -491,7 +500,7 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const bf16 *__restri
         stage();
         __syncthreads();
         for (int it = 0; it + 1 < nit; ++it) {
-            load(it + 1);  // in flight while this iteration's products run
+            load(it + 1);  // in flight while this step's products run
             __builtin_amdgcn_sched_barrier(0);
             compute();
             __syncthreads();
@@ -1096,17 +1105,28 @@ namespace {
 int wgrad_cib(int Ci) { return Ci == 16 ? 16 : Ci == 32 ? 32 : 64; }
 }  // namespace
 
-int conv3x3_wgrad_chunks(int B, int H, int W, int Ci, int Co)
+namespace {
+// Chunks of the weight gradient: about 1024 blocks in all (chunks x channel
+// tiles), each chunk `per` whole rows of one image, cpi chunks per image.
+void wgrad_split(int B, int H, int Ci, int Co, int &cpi, int &per)
 {
-    // about 1024 blocks in all (chunks x channel tiles), whole rows each
-    const long long rows = (long long)B * H;
     const int cib = wgrad_cib(Ci);
     const long long tiles = (long long)(Co / 16) * ((Ci + cib - 1) / cib);
-    long long chunks = (1024 + tiles - 1) / tiles;
-    if (chunks > rows) chunks = rows;
-    if (chunks < 1) chunks = 1;
+    const long long target = (1024 + tiles - 1) / tiles;
+    long long c = (target + B - 1) / B;
+    if (c > H) c = H;
+    if (c < 1) c = 1;
+    per = (int)((H + c - 1) / c);
+    cpi = (H + per - 1) / per;
+}
+}  // namespace
+
+int conv3x3_wgrad_chunks(int B, int H, int W, int Ci, int Co)
+{
+    int cpi = 0, per = 0;
+    wgrad_split(B, H, Ci, Co, cpi, per);
     (void)W;
-    return (int)chunks;
+    return B * cpi;
 }
 
 hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part, float *gw, int B, int H, int W,
@@ -1115,17 +1135,20 @@ hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part
     if (Ci % 16 || Co % 16 || B < 1 || H < 1 || W < 1) return hipErrorInvalidValue;
     // both tensors are addressed with 32-bit byte offsets (buffer loads)
     if ((long long)B * H * W * (Ci > Co ? Ci : Co) * 2 >= (1LL << 31)) return hipErrorInvalidValue;
-    const int chunks = conv3x3_wgrad_chunks(B, H, W, Ci, Co);
-    const int per = (int)(((long long)B * H + chunks - 1) / chunks);
+    int cpi = 0, per = 0;
+    wgrad_split(B, H, Ci, Co, cpi, per);
+    const int chunks = B * cpi;
     const int cib = wgrad_cib(Ci);
     const dim3 grid(chunks, (Co / 16) * ((Ci + cib - 1) / cib));
     const bf16 *d = static_cast<const bf16 *>(dpre), *x = static_cast<const bf16 *>(in);
-    if (cib == 16)
-        hipLaunchKernelGGL(conv3x3_wgrad_kernel<16>, grid, dim3(256), 0, s, d, x, part, B, H, W, Ci, Co, per);
-    else if (cib == 32)
-        hipLaunchKernelGGL(conv3x3_wgrad_kernel<32>, grid, dim3(256), 0, s, d, x, part, B, H, W, Ci, Co, per);
-    else
-        hipLaunchKernelGGL(conv3x3_wgrad_kernel<64>, grid, dim3(256), 0, s, d, x, part, B, H, W, Ci, Co, per);
+    // rows per step: up to four, no more than a chunk holds
+    const int rb = per >= 4 ? 4 : per >= 2 ? 2 : 1;
+#define RLBM_WGRAD(C, R)                                                                                      \
+    if (cib == C && rb == R)                                                                                  \
+        hipLaunchKernelGGL((conv3x3_wgrad_kernel<C, R>), grid, dim3(256), 0, s, d, x, part, B, H, W, Ci, Co, cpi, per);
+    RLBM_WGRAD(16, 1) RLBM_WGRAD(16, 2) RLBM_WGRAD(16, 4) RLBM_WGRAD(32, 1) RLBM_WGRAD(32, 2) RLBM_WGRAD(32, 4)
+    RLBM_WGRAD(64, 1) RLBM_WGRAD(64, 2) RLBM_WGRAD(64, 4)
+#undef RLBM_WGRAD
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long n = (long long)Co * 9 * Ci;

@@ -86,10 +86,13 @@ def test_conv3x3_forward_wide_images(ci, co, relu, H, W):
 
 @pytest.mark.parametrize("ci,co,B,H,W", [(16, 32, 2, 16, 32), (48, 16, 2, 16, 32), (80, 32, 3, 20, 48),
                                          (128, 16, 2, 160, 16), (16, 16, 1, 6, 256), (32, 16, 2, 3, 200),
-                                         (16, 32, 1, 34, 70)])
+                                         (16, 32, 1, 34, 70), (64, 64, 8, 64, 16), (128, 128, 8, 30, 16),
+                                         (16, 16, 8, 256, 16)])
 def test_conv3x3_backward_kernels_match_reference(ci, co, B, H, W):
     """Also partial 64-channel blocks, widths that are not a multiple of the
-    32-pixel segment, and several row chunks (320 rows of 16 pixels)."""
+    32-pixel segment, and several row chunks (320 rows of 16 pixels); the
+    last three shapes make the weight gradient take two or four rows per
+    step (batch 8), the second with a last chunk that runs past the image."""
     import paper_1804_02418_amd as rl
 
     torch = _torch()
