@@ -1106,13 +1106,13 @@ int wgrad_cib(int Ci) { return Ci == 16 ? 16 : Ci == 32 ? 32 : 64; }
 }  // namespace
 
 namespace {
-// Chunks of the weight gradient: about 1024 blocks in all (chunks x channel
+// Chunks of the weight gradient: about 512 blocks in all (chunks x channel
 // tiles), each chunk `per` whole rows of one image, cpi chunks per image.
 void wgrad_split(int B, int H, int Ci, int Co, int &cpi, int &per)
 {
     const int cib = wgrad_cib(Ci);
     const long long tiles = (long long)(Co / 16) * ((Ci + cib - 1) / cib);
-    const long long target = (1024 + tiles - 1) / tiles;
+    const long long target = (512 + tiles - 1) / tiles;
     long long c = (target + B - 1) / B;
     if (c > H) c = H;
     if (c < 1) c = 1;
