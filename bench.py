@@ -484,6 +484,43 @@ def surrogate_throughput(batch: int = 8, size: int = 256, steps: int = 20, warmu
             "forward_frac": round(fwd / (ms_infer / 1e3) / 1e12 / PEAK_BF16_TFLOPS, 4)}
 
 
+def surrogate_layers(batch: int = 8, size: int = 256, reps: int = 50):
+    """Each 3x3 convolution of the U-Net alone (rlbm_conv3x3_forward on random
+    BF16 tensors of the layer's shape, ReLU on): microseconds per call (HIP
+    events over `reps` calls after 3 untimed), TFLOP/s of its multiply-adds and
+    GB/s of its input plus output."""
+    import torch
+
+    from paper_1804_02418_amd import _binding as B
+    from paper_1804_02418_amd import surrogate as S
+
+    torch.manual_seed(0)
+    stream = torch.cuda.current_stream()
+    names = ["e1a", "e1b", "e2a", "e2b", "e3a", "e3b", "e4a", "e4b", "ba", "bb", "d4a", "d4b", "d3a", "d3b", "d2a",
+             "d2b", "d1a", "d1b"]
+    rows = []
+    for name, (lv, ci, co, k) in zip(names, S.layer_plan(16, S.CIN, S.COUT)):
+        H = W = size >> lv
+        x = torch.randn((batch, H, W, ci), device="cuda").to(torch.bfloat16)
+        w = (torch.randn((co, 3, 3, ci), device="cuda") / (9 * ci) ** 0.5).to(torch.bfloat16)
+        b = torch.randn(co, device="cuda")
+        y = torch.empty((batch, H, W, co), device="cuda", dtype=torch.bfloat16)
+        for _ in range(3):
+            B.conv3x3_forward(x, w, b, y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            B.conv3x3_forward(x, w, b, y)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        rows.append({"layer": name, "level": lv, "ci": ci, "co": co, "us": round(us, 2),
+                     "tflops": round(2.0 * batch * H * W * ci * co * 9 / us / 1e6, 1),
+                     "gbs": round(2.0 * batch * H * W * (ci + co) / us / 1e3, 1)})
+    return {"batch": batch, "size": size, "layers": rows, "sum_us": round(sum(r["us"] for r in rows), 1)}
+
+
 def cache_resident(w, storage) -> bool:
     """Both population arrays fit the 256 MB Infinity Cache (the step then
     need not stream from HBM)."""
@@ -508,6 +545,7 @@ def main(argv=None):
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate network throughput")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision legs")
     ap.add_argument("--surrogate-only", action="store_true", help="only time the surrogate network")
+    ap.add_argument("--surrogate-layers", action="store_true", help="only time each convolution of the network alone")
     ap.add_argument("--batch-only", action="store_true", help="only time the 256-sample batch")
     ap.add_argument("--bandwidth-probes", action="store_true",
                     help="only measure read, copy and 48-plane pull bandwidth (the practical ceilings)")
@@ -527,6 +565,9 @@ def main(argv=None):
         return 0
     if args.surrogate_only:
         print(json.dumps({"surrogate": surrogate_throughput()}), flush=True)
+        return 0
+    if args.surrogate_layers:
+        print(json.dumps({"surrogate_layers": surrogate_layers()}), flush=True)
         return 0
     if args.bandwidth_probes:
         for row in bandwidth_probes():
