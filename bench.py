@@ -287,7 +287,7 @@ def bandwidth_probes():
             g, u = B.bandwidth_probe(pattern, 4, nx, ny, nt, reps)
             rows.append({"pattern": pattern, "nontemporal": nt, "array_bytes": 48 * 4 * nx * ny, "GBs": round(g, 1),
                          "us": round(u, 2)})
-    for pattern in ("pull48", "pull48_pair"):
+    for pattern in ("pull48", "pull48_pair", "pull12_tuple", "pull24_tuple"):
         for elem, nx, ny, reps in ((4, 4096, 2048, 20), (2, 4096, 2048, 20), (8, 4096, 2048, 10), (4, 1024, 512, 200)):
             for nt in (False, True):
                 g, u = B.bandwidth_probe(pattern, elem, nx, ny, nt, reps)

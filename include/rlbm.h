@@ -60,7 +60,12 @@ typedef enum {
  *   RLBM_F32:    float32 storage, float32 arithmetic; moments are turned
  *                into the Landau frame in float64.
  *   RLBM_F16DEV: float16 storage of the scaled deviation, float32
- *                arithmetic, float64 Landau frame. */
+ *                arithmetic, float64 Landau frame.
+ * Device layout (seen only in the raw population part of a checkpoint):
+ * F64 and F32 hold 48 planes of nx*ny values, plane i = population i;
+ * F16DEV holds 12 arrays of nx*ny tuples, array d holding at each site the
+ * four shells of direction d (populations 4d .. 4d+3) in 8 bytes.  Every
+ * other call that takes or returns populations uses the 48-plane layout. */
 typedef enum { RLBM_F64 = 0, RLBM_F32 = 1, RLBM_F16DEV = 2 } rlbm_storage;
 
 typedef enum { RLBM_EDGE_BOTTOM = 0, RLBM_EDGE_TOP = 1, RLBM_EDGE_LEFT = 2, RLBM_EDGE_RIGHT = 3 } rlbm_edge;
@@ -100,7 +105,8 @@ rlbm_status rlbm_force_matrices(double Cx[256], double Cy[256]);
 
 /* ---- one lattice ---- */
 
-/* Create an nx x ny lattice (nx, ny >= 1) on the current HIP device.
+/* Create an nx x ny lattice (nx, ny >= 1, nx*ny < 2^31, one plane or
+ * tuple array below 4 GiB; RLBM_EINVAL otherwise) on the current HIP device.
  * hip_stream: a hipStream_t to order all work on (NULL = the null stream).
  * Defaults: all edges are walls, no contacts, no mask, tau = 1, no drive,
  * reference (n_ref, T_ref) = (1, 1), scale 1 (F64/F32) or 2^-12 (F16DEV).

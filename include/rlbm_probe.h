@@ -19,10 +19,16 @@ typedef enum {
     RLBM_PROBE_PULL48 = 2, /* the step's pattern: at every site with x, y in [5, n - 5), 48 loads from the
                               planes of the population layout, each shifted by its population's hop, and 48
                               aligned stores, with trivial arithmetic between them */
-    RLBM_PROBE_PULL48_PAIR = 3 /* the same with two adjacent sites (x even, x in [6, nx - 6)) per thread: each
+    RLBM_PROBE_PULL48_PAIR = 3, /* the same with two adjacent sites (x even, x in [6, nx - 6)) per thread: each
                                   plane read as one two-element load from the hop-shifted address (aligned to
                                   one element only for odd hops) and written as one aligned two-element store;
                                   nx must be even */
+    RLBM_PROBE_PULL12_TUPLE = 4, /* the step's pull in a direction-tuple layout: 12 arrays of nx ny tuples, a
+                                   tuple holding the four energy shells of one direction at one site (they
+                                   share the hop); per site with x, y in [5, n - 5), 12 hop-shifted tuple
+                                   loads (4 elem_bytes each) and 12 aligned tuple stores */
+    RLBM_PROBE_PULL24_TUPLE = 5 /* the same with tuples of two shells: 24 arrays, 24 loads and 24 stores of
+                                   2 elem_bytes per site */
 } rlbm_probe_pattern;
 
 /* Time `pattern` on arrays the size of one population array of an nx x ny

@@ -159,6 +159,59 @@ __global__ __launch_bounds__(256) void probe_pull48_pair(const T *__restrict__ s
     }
 }
 
+// Direction-tuple layouts: the shells of one direction hop alike, so W of
+// them (W = 4: all, W = 2: two) can sit together at each site: 48 / W
+// arrays of nx*ny tuples of W elements.  One interior site per thread:
+// 48 / W hop-shifted tuple loads, trivial arithmetic, 48 / W aligned tuple
+// stores.
+template <class T, int W, bool NT>
+__global__ __launch_bounds__(256) void probe_pull_tuple(const T *__restrict__ src, T *__restrict__ dst, int nx,
+                                                        int ny, long long P)
+{
+    typedef T V __attribute__((ext_vector_type(W)));
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int y = kReach + blockIdx.y;
+    if (x < kReach || x >= nx - kReach || y >= ny - kReach) return;
+    const long long site = (long long)y * nx + x;
+    const V *sv = reinterpret_cast<const V *>(src);
+    V *dv = reinterpret_cast<V *>(dst);
+    float h[kQ];
+#pragma unroll
+    for (int g = 0; g < kQ / W; ++g) {
+        const int d = g * W / kShells;
+        const V v = sv[(long long)g * P + site - ((long long)kCy[d] * nx + kCx[d])];
+#pragma unroll
+        for (int j = 0; j < W; ++j) h[W * g + j] = (float)v[j];
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) s += h[i];
+#pragma unroll
+    for (int g = 0; g < kQ / W; ++g) {
+        V v;
+#pragma unroll
+        for (int j = 0; j < W; ++j) v[j] = (T)(0.5f * h[W * g + j] + 1e-9f * s);
+        if constexpr (NT)
+            __builtin_nontemporal_store(v, &dv[(long long)g * P + site]);
+        else
+            dv[(long long)g * P + site] = v;
+    }
+}
+
+template <class T, int W>
+hipError_t launch_pull_tuple(const void *a, void *b, int nx, int ny, int nt, hipStream_t s)
+{
+    const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)(ny - 2 * kReach));
+    const long long P = (long long)nx * ny;
+    if (nt)
+        hipLaunchKernelGGL((probe_pull_tuple<T, W, true>), grid, dim3(256), 0, s, static_cast<const T *>(a),
+                           static_cast<T *>(b), nx, ny, P);
+    else
+        hipLaunchKernelGGL((probe_pull_tuple<T, W, false>), grid, dim3(256), 0, s, static_cast<const T *>(a),
+                           static_cast<T *>(b), nx, ny, P);
+    return hipGetLastError();
+}
+
 template <class T>
 hipError_t launch_pull_pair(const void *a, void *b, int nx, int ny, int nt, hipStream_t s)
 {
@@ -198,7 +251,7 @@ rlbm_status probe_fail(rlbm_status st, const char *what, hipError_t e)
 extern "C" rlbm_status rlbm_bandwidth_probe(int pattern, int elem_bytes, int nx, int ny, int nontemporal, int reps,
                                             void *hip_stream, double *gbs, double *us)
 {
-    if (pattern < RLBM_PROBE_READ || pattern > RLBM_PROBE_PULL48_PAIR ||
+    if (pattern < RLBM_PROBE_READ || pattern > RLBM_PROBE_PULL24_TUPLE ||
         (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) || nx <= 2 * kReach + 2 || ny <= 2 * kReach ||
         ny - 2 * kReach > 65535 || reps < 1 || (pattern == RLBM_PROBE_PULL48_PAIR && nx % 2))
         return set_error(RLBM_EINVAL, "rlbm_bandwidth_probe: invalid pattern, element size, size or repetitions");
@@ -234,6 +287,14 @@ extern "C" rlbm_status rlbm_bandwidth_probe(int pattern, int elem_bytes, int nx,
         }
         const void *from = (k & 1) ? b : a;
         void *to = (k & 1) ? a : b;
+        if (pattern == RLBM_PROBE_PULL12_TUPLE)
+            return elem_bytes == 2 ? launch_pull_tuple<_Float16, 4>(from, to, nx, ny, nontemporal, s)
+                   : elem_bytes == 4 ? launch_pull_tuple<float, 4>(from, to, nx, ny, nontemporal, s)
+                                     : launch_pull_tuple<double, 4>(from, to, nx, ny, nontemporal, s);
+        if (pattern == RLBM_PROBE_PULL24_TUPLE)
+            return elem_bytes == 2 ? launch_pull_tuple<_Float16, 2>(from, to, nx, ny, nontemporal, s)
+                   : elem_bytes == 4 ? launch_pull_tuple<float, 2>(from, to, nx, ny, nontemporal, s)
+                                     : launch_pull_tuple<double, 2>(from, to, nx, ny, nontemporal, s);
         if (pattern == RLBM_PROBE_PULL48_PAIR)
             return elem_bytes == 2 ? launch_pull_pair<_Float16>(from, to, nx, ny, nontemporal, s)
                    : elem_bytes == 4 ? launch_pull_pair<float>(from, to, nx, ny, nontemporal, s)

@@ -222,6 +222,7 @@ rlbm_status build_gather_table(rlbm_lattice *L, const std::vector<signed char> &
     // as a 32-bit byte offset from the array
     if (P * kQ >= (1LL << 31) || P * kQ * (long long)store_bytes(L->storage) >= (1LL << 32)) return RLBM_OK;
     const int nx = L->nx, ny = L->ny;
+    const int w = tuple_width((int)store_bytes(L->storage));
     const bool all = !has_interior(nx, ny, L->mask != nullptr);
     const long long nb = boundary_count(nx, ny, all);
     std::vector<unsigned> tab((size_t)nb * kQ);
@@ -238,7 +239,7 @@ rlbm_status build_gather_table(rlbm_lattice *L, const std::vector<signed char> &
             const bool inside = sx >= 0 && sx < nx && sy >= 0 && sy < ny;
             unsigned code;
             if (inside && !(L->mask && L->mask_host[(size_t)(sy * nx + sx)])) {
-                code = (unsigned)(i * P + sy * nx + sx);
+                code = (unsigned)pop_elem(w, i, sy * nx + sx, P);
             } else {
                 int c = -1;
                 if (!inside) {
@@ -247,7 +248,7 @@ rlbm_status build_gather_table(rlbm_lattice *L, const std::vector<signed char> &
                     else if (sx < 0 && sy >= 0 && sy < ny) c = edge[2 * nx + sy];
                     else if (sx >= nx && sy >= 0 && sy < ny) c = edge[2 * nx + ny + sy];
                 }
-                code = c >= 0 ? (kContactFlag | (unsigned)(c * kQ + i)) : (unsigned)(o * P + site);
+                code = c >= 0 ? (kContactFlag | (unsigned)(c * kQ + i)) : (unsigned)pop_elem(w, o, site, P);
             }
             tab[(size_t)i * nb + b] = code;
         }
@@ -430,8 +431,8 @@ rlbm_status rlbm_create(int nx, int ny, rlbm_storage storage, void *hip_stream, 
         return fail(RLBM_EINVAL, "rlbm_create: invalid size %d x %d", nx, ny);
     if (storage != RLBM_F64 && storage != RLBM_F32 && storage != RLBM_F16DEV)
         return fail(RLBM_EINVAL, "rlbm_create: unknown storage %d", (int)storage);
-    if ((long long)nx * ny * (long long)store_bytes(storage) >= (1LL << 32))
-        return fail(RLBM_EINVAL, "rlbm_create: one population plane of %d x %d exceeds 4 GiB", nx, ny);
+    if ((long long)nx * ny * (long long)store_bytes(storage) * tuple_width((int)store_bytes(storage)) >= (1LL << 32))
+        return fail(RLBM_EINVAL, "rlbm_create: one population plane (tuple array) of %d x %d exceeds 4 GiB", nx, ny);
     rlbm_lattice *L = new (std::nothrow) rlbm_lattice();
     if (!L) return fail(RLBM_ENOMEM, "rlbm_create: host allocation failed");
     rlbm_status st = load_constants(&L->C);

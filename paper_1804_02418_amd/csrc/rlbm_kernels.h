@@ -58,6 +58,20 @@ constexpr int kRestK[4] = {0, 1, 4, 9};
 constexpr int kMaxContacts = 16;
 constexpr unsigned kContactFlag = 0x80000000u;
 
+// Population layout of a storage: 48 / W arrays of nx*ny tuples, a tuple
+// holding W consecutive populations, i.e. W shells of one direction (the
+// four shells of a direction hop alike).  W = 1 is the plain layout of 48
+// planes (float64 and float32 storage); float16 storage keeps the four
+// shells of a direction in one 8-byte tuple, so that a pull reads each
+// direction as one 8-byte load per site (2-byte loads cap the pull well
+// below the bandwidth that 4- and 8-byte loads reach).
+__host__ __device__ constexpr int tuple_width(int store_bytes) { return store_bytes == 2 ? kShells : 1; }
+// Element index of population i at site s, P = nx*ny sites, tuples of w.
+__host__ __device__ constexpr long long pop_elem(int w, int i, long long s, long long P)
+{
+    return ((long long)(i / w) * P + s) * w + (i % w);
+}
+
 // Boundary part of the step grid: with an interior (nx, ny > 2 * reach, no
 // mask) the bottom and top bands of `reach` rows (the side columns of the
 // rows in between belong to the interior tiles, which resolve their few
@@ -116,7 +130,8 @@ struct StepArgs {
     int side_contacts;                // bit 0: the left edge has a contact span, bit 1: the right edge
     const R *contact_eta;             // [contact][48], eta units
     // boundary gather table [48][nbnd]: source element of population i of
-    // boundary site b (plane offset included), or kContactFlag | (c*48 + i)
+    // boundary site b (its index in the population array, pop_elem), or
+    // kContactFlag | (c*48 + i)
     // for a contact equilibrium; null -> the gather is computed in place
     const unsigned *gather_tab;
     long long nbnd;

@@ -50,6 +50,11 @@ struct StoreIO<_Float16> {
     __device__ static void store_nt(P p, R v) { __builtin_nontemporal_store(_Float16(float(v)), p); }
 };
 
+// Tuple of the four shells of one direction (float16 storage).
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
+template <class S>
+constexpr int kTup = tuple_width((int)sizeof(S));
+
 struct SiteFields {
     double n, u0, ux, uy, eps;  // density, Landau 4-velocity, energy density
 };
@@ -109,8 +114,51 @@ struct DeviceRecip {
 // Discards the post-collision values (callers that read h afterwards).
 struct NoEmit {
     template <class R>
-    __device__ void operator()(int, R) const {}
+    __device__ void operator()(int, R, const R *, const R *) const {}
 };
+
+// Two float16 values a * h0 + q0 and a * h1 + q1, each rounded once from
+// the exact a * h + q (mixed-precision FMA), packed low / high in 32 bits.
+// Written out so that every kernel rounds alike: left to the compiler,
+// some values became an FMA rounded to float32 and then converted (two
+// roundings), differently in different kernels.
+__device__ __forceinline__ unsigned fma_pack_f16(float a, float h0, float q0, float h1, float q1)
+{
+    unsigned r = 0;
+    asm("v_fma_mixlo_f16 %0, %1, %2, %3" : "+v"(r) : "v"(a), "v"(h0), "v"(q0));
+    asm("v_fma_mixhi_f16 %0, %1, %2, %3" : "+v"(r) : "v"(a), "v"(h1), "v"(q1));
+    return r;
+}
+
+// Stores the four post-collision values v of direction d of one site into
+// the population array dst (P sites per plane or tuple array): four plane
+// elements, or one tuple in float16 storage.  site_bytes is the site's
+// offset in bytes within one plane, or within one tuple array (site times
+// sizeof(S) times the tuple width).
+template <class S, class R, bool NT>
+__device__ __forceinline__ void store_dir(S *__restrict__ dst, long long P, int d, unsigned site_bytes, R a,
+                                          const R *h, const R *q)
+{
+    if constexpr (kTup<S> == kShells) {
+        typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+        const u32x2 t = {fma_pack_f16(a, h[0], q[0], h[1], q[1]), fma_pack_f16(a, h[2], q[2], h[3], q[3])};
+        auto p = plane_at_bytes(reinterpret_cast<u32x2 *>(dst) + (long long)d * P, site_bytes);
+        if constexpr (NT)
+            __builtin_nontemporal_store(t, p);
+        else
+            *p = t;
+    } else {
+#pragma unroll
+        for (int j = 0; j < kShells; ++j) {
+            auto p = plane_at_bytes(dst + (long long)(kShells * d + j) * P, site_bytes);
+            const R v = a * h[j] + q[j];
+            if constexpr (NT)
+                StoreIO<S>::template store_nt<R>(p, v);
+            else
+                StoreIO<S>::template store<R>(p, v);
+        }
+    }
+}
 // Discards the site's fields.
 struct NoFields {
     __device__ void operator()(const SiteFields &, bool) const {}
@@ -121,8 +169,10 @@ struct NoFields {
 // equilibrium and forcing polynomials -> relaxation with
 // omega_d = p_i.U / (p0_i tau) = (U^0 - nhat_d . U_s) / tau.
 // fields(f, ok) receives the site's fields right after the Landau frame and
-// emit(i, value) each post-collision value as soon as it is formed, so a
-// caller that stores them lets their registers die early.
+// emit(d, a, h, q) the four post-collision values of direction d,
+// a * h[j] + q[j] for shell j (a = 1 - omega_d, h the pre-collision values),
+// as soon as their terms are formed, so a caller that stores them lets their
+// registers die early; h itself is left as it was.
 template <class R, class Emit = NoEmit, class Fields = NoFields>
 __device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, R fx, R fy, bool has_force,
                                              const Emit &emit = Emit(), const Fields &fields = Fields())
@@ -220,16 +270,17 @@ __device__ __forceinline__ bool collide_site(R (&h)[kQ], const StepArgs<R> &A, R
         omega_pair(Wc, Ws, tg, E, O);
         const R proj = Ux * R(tg.c) + Uy * R(tg.s);
         const R wp = U0 - proj, wm = U0 + proj;  // omega of d and of d + 6
+        R Qp[kShells], Qm[kShells];
 #pragma unroll
         for (int j = 0; j < kShells; ++j) {
             const R p = A.p0[j];
             const R qp = (((E[3] + O[3]) * p + (E[2] + O[2])) * p + (E[1] + O[1])) * p + (E[0] + O[0]);
             const R qm = (((E[3] - O[3]) * p + (E[2] - O[2])) * p + (E[1] - O[1])) * p + (E[0] - O[0]);
-            h[4 * d + j] = (R(1) - wp) * h[4 * d + j] + qp;
-            h[4 * (d + 6) + j] = (R(1) - wm) * h[4 * (d + 6) + j] + qm;
-            emit(4 * d + j, h[4 * d + j]);
-            emit(4 * (d + 6) + j, h[4 * (d + 6) + j]);
+            Qp[j] = qp;
+            Qm[j] = qm;
         }
+        emit(d, R(1) - wp, &h[4 * d], Qp);
+        emit(d + 6, R(1) - wm, &h[4 * (d + 6)], Qm);
     }
     return ok;
 }
@@ -315,7 +366,7 @@ __device__ __forceinline__ void gather_general(const StepArgs<R> &A, const S *__
         const bool pull = inside && !(A.has_mask && A.mask[s2]);
         R v;
         if (pull) {
-            v = StoreIO<S>::template load<R>(src + (long long)i * P + s2);
+            v = StoreIO<S>::template load<R>(src + pop_elem(kTup<S>, i, s2, P));
         } else {
             int c = -1;
             if (!inside) {
@@ -328,7 +379,7 @@ __device__ __forceinline__ void gather_general(const StepArgs<R> &A, const S *__
                 else if (sx >= nx && (unsigned)sy < (unsigned)ny)
                     c = A.edge_contact[2 * nx + ny + sy];
             }
-            v = c >= 0 ? A.contact_eta[c * kQ + i] : StoreIO<S>::template load<R>(src + (long long)o * P + site);
+            v = c >= 0 ? A.contact_eta[c * kQ + i] : StoreIO<S>::template load<R>(src + pop_elem(kTup<S>, o, site, P));
         }
         h[i] = v;
     }
@@ -353,7 +404,36 @@ __device__ __forceinline__ void side_wave_gather(const StepArgs<R> &A, const S *
 {
     const int nx = A.nx;
     const long long P = A.plane;
-    if constexpr (OFF32) {
+    if constexpr (kTup<S> == kShells) {
+        // one tuple (all four shells) per direction; e indexes tuples
+#pragma unroll
+        for (int d = 0; d < kDirs; ++d) {
+            const int sx = x - kCx[d];
+            half4 v;
+            if constexpr (OFF32) {
+                const unsigned Pu = (unsigned)P;
+                unsigned e = (unsigned)d * Pu + (unsigned)((y - kCy[d]) * nx + sx);  // plain pull
+                if (kCx[d] != 0) {
+                    const bool out = (unsigned)sx >= (unsigned)nx;
+                    const unsigned wrapped = e + (unsigned)(sx < 0 ? nx : -nx);
+                    const unsigned bounce = (unsigned)((d + kDirs / 2) % kDirs) * Pu + site;
+                    e = out ? (A.periodic_x ? wrapped : bounce) : e;
+                }
+                v = *plane_at_bytes(reinterpret_cast<const half4 *>(src), e * (unsigned)sizeof(half4));
+            } else {
+                long long e = (long long)d * P + (long long)(y - kCy[d]) * nx + sx;  // plain pull
+                if (kCx[d] != 0) {
+                    const bool out = (unsigned)sx >= (unsigned)nx;
+                    const long long wrapped = e + (sx < 0 ? nx : -nx);
+                    const long long bounce = (long long)((d + kDirs / 2) % kDirs) * P + site;
+                    e = out ? (A.periodic_x ? wrapped : bounce) : e;
+                }
+                v = reinterpret_cast<const half4 *>(src)[e];
+            }
+#pragma unroll
+            for (int j = 0; j < kShells; ++j) h[kShells * d + j] = R(float(v[j]));
+        }
+    } else if constexpr (OFF32) {
         const unsigned Pu = (unsigned)P;
 #pragma unroll
         for (int i = 0; i < kQ; ++i) {
@@ -522,24 +602,31 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
         }
     } else {
         // uniform plane base pointers + one 32-bit site offset
+        if constexpr (kTup<S> == kShells) {
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-            const int d = i / kShells;
-            const S *__restrict__ plane = src + ((long long)i * P - ((long long)kCy[d] * nx + kCx[d]));
-            h[i] = StoreIO<S>::template load<R>(plane_at(plane, site));
+            for (int d = 0; d < kDirs; ++d) {
+                const half4 *__restrict__ arr =
+                    reinterpret_cast<const half4 *>(src) + ((long long)d * P - ((long long)kCy[d] * nx + kCx[d]));
+                const half4 v = *plane_at(arr, site);
+#pragma unroll
+                for (int j = 0; j < kShells; ++j) h[kShells * d + j] = R(float(v[j]));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) {
+                const int d = i / kShells;
+                const S *__restrict__ plane = src + ((long long)i * P - ((long long)kCy[d] * nx + kCx[d]));
+                h[i] = StoreIO<S>::template load<R>(plane_at(plane, site));
+            }
         }
     }
     // ---- collide; each post-collision value is stored as soon as it is
     // formed (streaming stores bypass the caches: the next step reads every
     // value once) ----
-    unsigned site_bytes = site * (unsigned)sizeof(S);
-    auto store = [&](int i, R v) {
+    unsigned site_bytes = site * (unsigned)(sizeof(S) * kTup<S>);
+    auto store = [&](int d, R a, const R *hv, const R *q) {
         asm volatile("" : "+v"(site_bytes));
-        auto p = plane_at_bytes(dst + (long long)i * P, site_bytes);
-        if constexpr (NT)
-            StoreIO<S>::template store_nt<R>(p, v);
-        else
-            StoreIO<S>::template store<R>(p, v);
+        store_dir<S, R, NT>(dst, P, d, site_bytes, a, hv, q);
     };
     auto fields = [&](const SiteFields &f, bool ok) {
         if (wf) write_fields(A, site, f, ok);
@@ -641,7 +728,7 @@ __global__ __launch_bounds__(256) void init_kernel(const StepArgs<R> A, const do
     if (site >= A.plane) return;
     if (A.has_mask && A.mask[site]) {
         if (mode == kInitDensity) return;
-        for (int i = 0; i < kQ; ++i) StoreIO<S>::template store<R>(dst + (long long)i * A.plane + site, R(0));
+        for (int i = 0; i < kQ; ++i) StoreIO<S>::template store<R>(dst + pop_elem(kTup<S>, i, site, A.plane), R(0));
         A.fn[site] = 0.0;
         A.fvx[site] = 0.0;
         A.fvy[site] = 0.0;
@@ -683,7 +770,16 @@ __global__ __launch_bounds__(256) void init_kernel(const StepArgs<R> A, const do
         return;
     }
     collide_site<R>(h, A, fx, fy, force,
-                    [&](int i, R v) { StoreIO<S>::template store<R>(dst + (long long)i * A.plane + site, v); },
+                    [&](int d, R a, const R *hv, const R *q) {
+                        if constexpr (kTup<S> == kShells) {
+                            store_dir<S, R, false>(dst, A.plane, d, (unsigned)site * (unsigned)sizeof(half4), a, hv, q);
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < kShells; ++j)
+                                StoreIO<S>::template store<R>(dst + pop_elem(1, kShells * d + j, site, A.plane),
+                                                              a * hv[j] + q[j]);
+                        }
+                    },
                     [&](const SiteFields &f, bool ok) { write_fields(A, site, f, ok); });
 }
 
@@ -695,7 +791,7 @@ __global__ __launch_bounds__(256) void decode_kernel(long long plane, const S *_
     const long long site = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (site >= plane) return;
     for (int i = 0; i < kQ; ++i) {
-        const double e = StoreIO<S>::template load<double>(src + (long long)i * plane + site);
+        const double e = StoreIO<S>::template load<double>(src + pop_elem(kTup<S>, i, site, plane));
         f[(long long)i * plane + site] = fref[i] + wscale[i] * e;
     }
 }
