@@ -124,8 +124,9 @@ struct NoEmit {
 // roundings), differently in different kernels.
 __device__ __forceinline__ unsigned fma_pack_f16(float a, float h0, float q0, float h1, float q1)
 {
-    unsigned r = 0;
-    asm("v_fma_mixlo_f16 %0, %1, %2, %3" : "+v"(r) : "v"(a), "v"(h0), "v"(q0));
+    // the low half is written first (the high half it leaves is overwritten next)
+    unsigned r;
+    asm("v_fma_mixlo_f16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(h0), "v"(q0));
     asm("v_fma_mixhi_f16 %0, %1, %2, %3" : "+v"(r) : "v"(a), "v"(h1), "v"(q1));
     return r;
 }
@@ -518,9 +519,11 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
     } else {
         const int tb = b - nbnd;
         const int by = tb / tiles_x, bx = tb - by * tiles_x;
-        const int rows = blockDim.x / tile_x;
-        const int ty = t / tile_x;
-        x = bx * tile_x + (t - ty * tile_x);
+        // tile_x is 64, 128 or 256 (tile_x * rows = 256): shifts, not divisions
+        const int lg = 31 - __builtin_clz(tile_x);
+        const int rows = (int)blockDim.x >> lg;
+        const int ty = t >> lg;
+        x = bx * tile_x + (t & (tile_x - 1));
         y = kReach + by * rows + ty;
         if (x >= nx || y >= A.ny - kReach) return;
     }
