@@ -293,6 +293,15 @@ def bandwidth_probes():
                 g, u = B.bandwidth_probe(pattern, elem, nx, ny, nt, reps)
                 rows.append({"pattern": pattern, "elem_bytes": elem, "nx": nx, "ny": ny, "nontemporal": nt,
                              "GBs": round(g, 1), "us": round(u, 2)})
+    # 64 x 4 blocks, also on narrow lattices of about the same site count (a
+    # batch's samples are a few hundred sites wide)
+    for pattern in ("pull48_t64", "pull24_tuple_t64", "pull12_tuple_t64"):
+        for elem, nx, ny, reps in ((4, 4096, 2048, 20), (4, 320, 26214, 20), (4, 192, 43690, 20), (2, 4096, 2048, 20),
+                                   (2, 320, 26214, 20), (8, 4096, 2048, 10)):
+            for nt in (False, True):
+                g, u = B.bandwidth_probe(pattern, elem, nx, ny, nt, reps)
+                rows.append({"pattern": pattern, "elem_bytes": elem, "nx": nx, "ny": ny, "nontemporal": nt,
+                             "GBs": round(g, 1), "us": round(u, 2)})
     rows.append(dict(pattern="torch device copy", **copy_calibration(1 << 30)))
     return rows
 

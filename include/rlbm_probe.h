@@ -27,8 +27,12 @@ typedef enum {
                                    tuple holding the four energy shells of one direction at one site (they
                                    share the hop); per site with x, y in [5, n - 5), 12 hop-shifted tuple
                                    loads (4 elem_bytes each) and 12 aligned tuple stores */
-    RLBM_PROBE_PULL24_TUPLE = 5 /* the same with tuples of two shells: 24 arrays, 24 loads and 24 stores of
-                                   2 elem_bytes per site */
+    RLBM_PROBE_PULL24_TUPLE = 5, /* the same with tuples of two shells: 24 arrays, 24 loads and 24 stores of
+                                    2 elem_bytes per site */
+    RLBM_PROBE_PULL48_T64 = 6,        /* PULL48 by blocks of 64 x 4 sites (the other pull patterns use blocks of
+                                         256 x 1 sites) */
+    RLBM_PROBE_PULL24_TUPLE_T64 = 7,  /* PULL24_TUPLE by blocks of 64 x 4 sites */
+    RLBM_PROBE_PULL12_TUPLE_T64 = 8   /* PULL12_TUPLE by blocks of 64 x 4 sites */
 } rlbm_probe_pattern;
 
 /* Time `pattern` on arrays the size of one population array of an nx x ny

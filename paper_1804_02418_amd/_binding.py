@@ -445,7 +445,8 @@ class NotFound(RlbmError):
     pass
 
 
-PROBE_PATTERNS = {"read": 0, "copy": 1, "pull48": 2, "pull48_pair": 3, "pull12_tuple": 4, "pull24_tuple": 5}
+PROBE_PATTERNS = {"read": 0, "copy": 1, "pull48": 2, "pull48_pair": 3, "pull12_tuple": 4, "pull24_tuple": 5,
+                  "pull48_t64": 6, "pull24_tuple_t64": 7, "pull12_tuple_t64": 8}
 
 
 def bandwidth_probe(pattern: str, elem_bytes: int, nx: int, ny: int, nontemporal: bool = False, reps: int = 10,

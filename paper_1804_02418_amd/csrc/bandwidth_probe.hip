@@ -164,13 +164,14 @@ __global__ __launch_bounds__(256) void probe_pull48_pair(const T *__restrict__ s
 // arrays of nx*ny tuples of W elements.  One interior site per thread:
 // 48 / W hop-shifted tuple loads, trivial arithmetic, 48 / W aligned tuple
 // stores.
-template <class T, int W, bool NT>
+template <class T, int W, int TX, bool NT>
 __global__ __launch_bounds__(256) void probe_pull_tuple(const T *__restrict__ src, T *__restrict__ dst, int nx,
                                                         int ny, long long P)
 {
     typedef T V __attribute__((ext_vector_type(W)));
-    const int x = blockIdx.x * 256 + threadIdx.x;
-    const int y = kReach + blockIdx.y;
+    // blocks of TX x (256 / TX) sites, as the step's tiles
+    const int x = blockIdx.x * TX + (int)(threadIdx.x % TX);
+    const int y = kReach + blockIdx.y * (256 / TX) + (int)(threadIdx.x / TX);
     if (x < kReach || x >= nx - kReach || y >= ny - kReach) return;
     const long long site = (long long)y * nx + x;
     const V *sv = reinterpret_cast<const V *>(src);
@@ -198,16 +199,16 @@ __global__ __launch_bounds__(256) void probe_pull_tuple(const T *__restrict__ sr
     }
 }
 
-template <class T, int W>
+template <class T, int W, int TX = 256>
 hipError_t launch_pull_tuple(const void *a, void *b, int nx, int ny, int nt, hipStream_t s)
 {
-    const dim3 grid((unsigned)((nx + 255) / 256), (unsigned)(ny - 2 * kReach));
+    const dim3 grid((unsigned)((nx + TX - 1) / TX), (unsigned)((ny - 2 * kReach + 256 / TX - 1) / (256 / TX)));
     const long long P = (long long)nx * ny;
     if (nt)
-        hipLaunchKernelGGL((probe_pull_tuple<T, W, true>), grid, dim3(256), 0, s, static_cast<const T *>(a),
+        hipLaunchKernelGGL((probe_pull_tuple<T, W, TX, true>), grid, dim3(256), 0, s, static_cast<const T *>(a),
                            static_cast<T *>(b), nx, ny, P);
     else
-        hipLaunchKernelGGL((probe_pull_tuple<T, W, false>), grid, dim3(256), 0, s, static_cast<const T *>(a),
+        hipLaunchKernelGGL((probe_pull_tuple<T, W, TX, false>), grid, dim3(256), 0, s, static_cast<const T *>(a),
                            static_cast<T *>(b), nx, ny, P);
     return hipGetLastError();
 }
@@ -251,7 +252,7 @@ rlbm_status probe_fail(rlbm_status st, const char *what, hipError_t e)
 extern "C" rlbm_status rlbm_bandwidth_probe(int pattern, int elem_bytes, int nx, int ny, int nontemporal, int reps,
                                             void *hip_stream, double *gbs, double *us)
 {
-    if (pattern < RLBM_PROBE_READ || pattern > RLBM_PROBE_PULL24_TUPLE ||
+    if (pattern < RLBM_PROBE_READ || pattern > RLBM_PROBE_PULL12_TUPLE_T64 ||
         (elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) || nx <= 2 * kReach + 2 || ny <= 2 * kReach ||
         ny - 2 * kReach > 65535 || reps < 1 || (pattern == RLBM_PROBE_PULL48_PAIR && nx % 2))
         return set_error(RLBM_EINVAL, "rlbm_bandwidth_probe: invalid pattern, element size, size or repetitions");
@@ -295,6 +296,20 @@ extern "C" rlbm_status rlbm_bandwidth_probe(int pattern, int elem_bytes, int nx,
             return elem_bytes == 2 ? launch_pull_tuple<_Float16, 2>(from, to, nx, ny, nontemporal, s)
                    : elem_bytes == 4 ? launch_pull_tuple<float, 2>(from, to, nx, ny, nontemporal, s)
                                      : launch_pull_tuple<double, 2>(from, to, nx, ny, nontemporal, s);
+        if (pattern >= RLBM_PROBE_PULL48_T64) {
+            const int w = pattern == RLBM_PROBE_PULL48_T64 ? 1 : pattern == RLBM_PROBE_PULL24_TUPLE_T64 ? 2 : 4;
+            if (elem_bytes == 2)
+                return w == 1 ? launch_pull_tuple<_Float16, 1, 64>(from, to, nx, ny, nontemporal, s)
+                       : w == 2 ? launch_pull_tuple<_Float16, 2, 64>(from, to, nx, ny, nontemporal, s)
+                                : launch_pull_tuple<_Float16, 4, 64>(from, to, nx, ny, nontemporal, s);
+            if (elem_bytes == 4)
+                return w == 1 ? launch_pull_tuple<float, 1, 64>(from, to, nx, ny, nontemporal, s)
+                       : w == 2 ? launch_pull_tuple<float, 2, 64>(from, to, nx, ny, nontemporal, s)
+                                : launch_pull_tuple<float, 4, 64>(from, to, nx, ny, nontemporal, s);
+            return w == 1 ? launch_pull_tuple<double, 1, 64>(from, to, nx, ny, nontemporal, s)
+                   : w == 2 ? launch_pull_tuple<double, 2, 64>(from, to, nx, ny, nontemporal, s)
+                            : launch_pull_tuple<double, 4, 64>(from, to, nx, ny, nontemporal, s);
+        }
         if (pattern == RLBM_PROBE_PULL48_PAIR)
             return elem_bytes == 2 ? launch_pull_pair<_Float16>(from, to, nx, ny, nontemporal, s)
                    : elem_bytes == 4 ? launch_pull_pair<float>(from, to, nx, ny, nontemporal, s)

@@ -236,7 +236,8 @@ def test_bandwidth_probe_runs_every_pattern():
 
     for pattern, elem in (("read", 4), ("copy", 4), ("pull48", 2), ("pull48", 4), ("pull48", 8), ("pull12_tuple", 2),
                           ("pull12_tuple", 4), ("pull12_tuple", 8), ("pull24_tuple", 2), ("pull24_tuple", 4),
-                          ("pull24_tuple", 8)):
+                          ("pull24_tuple", 8), ("pull48_t64", 4), ("pull24_tuple_t64", 4), ("pull12_tuple_t64", 2),
+                          ("pull12_tuple_t64", 8)):
         for nt in (False, True):
             g, u = B.bandwidth_probe(pattern, elem, 203, 77, nt, 3)
             assert np.isfinite(g) and g > 0 and u > 0, (pattern, elem, nt, g, u)

@@ -122,7 +122,7 @@ def test_bandwidth_probe_rejects_bad_arguments():
     import paper_1804_02418_amd as rl
     from paper_1804_02418_amd import _binding as B
 
-    for args in ((6, 4, 64, 64, 0, 1), (-1, 4, 64, 64, 0, 1), (0, 3, 64, 64, 0, 1), (2, 4, 10, 64, 0, 1), (2, 4, 64, 10, 0, 1),
+    for args in ((9, 4, 64, 64, 0, 1), (-1, 4, 64, 64, 0, 1), (0, 3, 64, 64, 0, 1), (2, 4, 10, 64, 0, 1), (2, 4, 64, 10, 0, 1),
                  (2, 4, 64, 70000, 0, 1), (1, 4, 64, 64, 0, 0)):
         st = rl.lib().rlbm_bandwidth_probe(*args, None, None, None)
         assert st == B.EINVAL, (args, st)
