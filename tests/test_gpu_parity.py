@@ -176,6 +176,30 @@ def test_checkpoint_restore_is_bit_identical():
         assert np.array_equal(fa[k], fb[k])
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+def test_checkpoint_population_layout(storage):
+    """The raw populations of a checkpoint follow the documented device
+    layout (include/rlbm.h): 48 planes for FP64 and FP32, 12 arrays of
+    four-shell direction tuples for FP16.  Read in that layout, each
+    population's raw values map onto its decoded values by one affine map
+    f = f_ref + w scale eta over every site (to rounding); any other reading
+    of the layout mixes populations or sites and breaks it."""
+    w = workloads.small_device(nx=70, ny=30, steps=3)
+    G = gpu_lattice(w, storage)
+    G.step(3)
+    P = w["nx"] * w["ny"]
+    dt = {"f64": np.float64, "f32": np.float32, "f16dev": np.float16}[storage]
+    raw = np.frombuffer(G.get_state(), dtype=dt, count=48 * P, offset=72).astype(np.float64)
+    eta = raw.reshape(12, P, 4).transpose(0, 2, 1).reshape(48, P) if storage == "f16dev" else raw.reshape(48, P)
+    f = G.read_populations().reshape(48, P)
+    for i in range(48):
+        assert np.ptp(eta[i]) > 0, i
+        b, a = np.polyfit(eta[i], f[i], 1)
+        res = np.abs(f[i] - (a + b * eta[i])).max()
+        assert res <= 1e-12 * np.abs(f[i]).max(), (storage, i, res)
+    G.close()
+
+
 def test_invalid_tau_and_unstable_state():
     import paper_1804_02418_amd as rl
 
