@@ -386,6 +386,64 @@ __device__ __forceinline__ void gather_general(const StepArgs<R> &A, const S *__
     }
 }
 
+// Loads of a wave of the top or bottom boundary band of a lattice with an
+// interior (no solid mask, nx and ny above twice the stencil's reach, so
+// one wrap brings any source back onto a periodic axis).  Per direction:
+// the source site after the periodic wraps, or, for a source off the
+// lattice, bounce-back from the site itself (the opposite direction's
+// value there); then a source in a contact's ghost span (off the lattice
+// beyond exactly one edge) takes the span's equilibrium.  The rules and
+// their precedence are gather_general's; here every lane loads every
+// direction at a selected 32-bit offset (no branch around a load, no table
+// codes to read: the population array is below 4 GiB whenever the lattice
+// has a gather table, the only case that calls this).
+template <class S, class R>
+__device__ __forceinline__ void band_wave_gather(const StepArgs<R> &A, const S *__restrict__ src, int x, int y,
+                                                 unsigned site, R (&h)[kQ])
+{
+    const int nx = A.nx, ny = A.ny;
+    const unsigned Pu = (unsigned)A.plane;
+    int cdir[kDirs];
+    bool any = false;
+#pragma unroll
+    for (int d = 0; d < kDirs; ++d) {
+        int sx = x - kCx[d], sy = y - kCy[d];
+        if (A.periodic_x) sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+        if (A.periodic_y) sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+        const bool xin = (unsigned)sx < (unsigned)nx, yin = (unsigned)sy < (unsigned)ny;
+        const bool pull = xin & yin;
+        const unsigned dd = pull ? (unsigned)d : (unsigned)((d + kDirs / 2) % kDirs);
+        const unsigned ss = pull ? (unsigned)(sy * nx + sx) : site;
+        if constexpr (kTup<S> == kShells) {
+            const half4 v = *plane_at_bytes(reinterpret_cast<const half4 *>(src), (dd * Pu + ss) * (unsigned)sizeof(half4));
+#pragma unroll
+            for (int j = 0; j < kShells; ++j) h[kShells * d + j] = R(float(v[j]));
+        } else {
+            const unsigned e0 = kShells * dd * Pu + ss;
+#pragma unroll
+            for (int j = 0; j < kShells; ++j)
+                h[kShells * d + j] =
+                    StoreIO<S>::template load<R>(plane_at_bytes(src, (e0 + (unsigned)j * Pu) * (unsigned)sizeof(S)));
+        }
+        // edge table entry of a source beyond exactly one edge, else none
+        const int ei = (xin & !yin) ? (sy < 0 ? sx : nx + sx) : (!xin & yin) ? (sx < 0 ? 2 * nx : 2 * nx + ny) + sy : -1;
+        const int c = A.edge_contact[ei < 0 ? 0 : ei];
+        cdir[d] = ei < 0 ? -1 : c;
+        any = any || cdir[d] >= 0;
+    }
+    if (__ballot(any)) {
+#pragma unroll
+        for (int d = 0; d < kDirs; ++d) {
+            const int cc = cdir[d] < 0 ? 0 : cdir[d];
+#pragma unroll
+            for (int j = 0; j < kShells; ++j) {
+                const R v = A.contact_eta[cc * kQ + kShells * d + j];
+                h[kShells * d + j] = cdir[d] >= 0 ? v : h[kShells * d + j];
+            }
+        }
+    }
+}
+
 // Loads of a wave that holds side columns of an interior row (x < reach or
 // x >= nx - reach).  For a side lane, the populations whose source lies
 // beyond the left or right edge follow the boundary rules of the pull:
@@ -549,7 +607,9 @@ __device__ __forceinline__ void step_block(const StepArgs<R> &A, const S *__rest
     R h[kQ];
     if (bnd) {
         const bool table = GATHER == kGatherTable || (GATHER == kGatherEither && A.gather_tab);
-        if (table) {
+        if (table && !all) {
+            band_wave_gather<S, R>(A, src, x, y, site, h);
+        } else if (table) {
             // eight table codes, then their eight values, at a time, the
             // codes of the next eight already in flight: the band's path then
             // waits for about four memory round trips instead of twelve, and
