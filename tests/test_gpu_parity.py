@@ -78,8 +78,8 @@ def test_masked_obstacle_periodic_x_matches_oracle():
 def test_contacts_on_every_edge_match_oracle(periodic_y):
     """Contact spans on all four edges, two of them reaching the corners: the
     side columns of the interior rows (left and right contacts and walls,
-    resolved inside the row tiles) and the top and bottom bands (gather
-    table) both meet every boundary rule."""
+    resolved inside the row tiles) and the top and bottom bands (sources
+    picked per lane) both meet every boundary rule."""
     w = workloads.small_device(nx=150, ny=60, steps=40)
     c = w["contacts"]
     w["contacts"] = [dict(c[0], edge="bottom", start=10, width=30), dict(c[2], edge="top", start=100, width=50),
@@ -87,6 +87,23 @@ def test_contacts_on_every_edge_match_oracle(periodic_y):
     if periodic_y:
         w.update(periodic_y=True, contacts=[k for k in w["contacts"] if k["edge"] in ("left", "right")])
     _compare_run(w, [0, 1, 5, 40])
+
+
+@pytest.mark.parametrize("periodic_x,periodic_y", [(False, False), (True, False), (False, True), (True, True)])
+def test_smallest_interior_lattices_match_oracle(periodic_x, periodic_y):
+    """11 x 11 and 13 x 12, the smallest lattices with an interior: every
+    site but one row or column lies in a band or a side column, the bands'
+    sources wrap once on a periodic axis, and contact spans cover whole
+    edges (every corner rule)."""
+    for nx, ny in ((11, 11), (13, 12)):
+        w = workloads.small_device(nx=nx, ny=ny, steps=12)
+        c = w["contacts"][0]
+        spans = [dict(c, edge="bottom", start=0, width=nx), dict(c, edge="top", start=2, width=nx - 4),
+                 dict(c, edge="left", start=0, width=ny), dict(c, edge="right", start=3, width=ny - 3)]
+        w.update(periodic_x=periodic_x, periodic_y=periodic_y,
+                 contacts=[k for k in spans if not (periodic_x and k["edge"] in ("left", "right"))
+                           and not (periodic_y and k["edge"] in ("bottom", "top"))])
+        _compare_run(w, [0, 1, 12])
 
 
 @pytest.mark.parametrize("nx,ny", [(1, 6), (3, 7), (5, 2), (70, 3)])
