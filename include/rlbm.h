@@ -252,6 +252,17 @@ rlbm_status rlbm_get_launch_shape(rlbm_lattice *lat, int *tile_x, int *rows);
  * blocks alternate between XCDs.  Results are identical either way. */
 rlbm_status rlbm_set_block_order(rlbm_lattice *lat, int xcd_contiguous);
 
+/* Boundary gather table: enabled = 1 (default) lets the lattice build its
+ * host-side table of boundary sources (every site of a lattice with a solid
+ * mask or no interior) whenever its population array is below 4 GiB;
+ * enabled = 0 drops it, and the kernels then resolve every boundary source
+ * in place with 64-bit addressing, as they do for lattices of 4 GiB and
+ * more, which never have a table: the way to exercise that path at small
+ * sizes.  Results are identical either way.  RLBM_EINVAL for other values;
+ * takes effect for the next step (the table is rebuilt or freed at once,
+ * synchronising the lattice's stream). */
+rlbm_status rlbm_set_gather_table(rlbm_lattice *lat, int enabled);
+
 /* Streaming (non-temporal) stores of the populations: on = 1 launches the
  * form of the step kernel whose stores bypass the caches.  Pays off once the
  * two population arrays outgrow the 256 MB Infinity Cache (the default

@@ -92,6 +92,7 @@ SIGNATURES = {
     "rlbm_get_launch_shape": ([_vp, _ip, _ip], None),
     "rlbm_autotune": ([_vp, ctypes.c_int, _dp], None),
     "rlbm_set_streaming_stores": ([_vp, ctypes.c_int], None),
+    "rlbm_set_gather_table": ([_vp, ctypes.c_int], None),
     "rlbm_synchronize": ([_vp], None),
     "rlbm_batch_create": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)], None),
     "rlbm_batch_destroy": ([_vp], "void"),
@@ -340,6 +341,11 @@ class Lattice:
 
     def set_streaming_stores(self, on: bool):
         check(lib().rlbm_set_streaming_stores(self._h, int(bool(on))))
+
+    def set_gather_table(self, enabled: bool):
+        """False: resolve every boundary source in place, as lattices of 4 GiB
+        and more do (include/rlbm.h)."""
+        check(lib().rlbm_set_gather_table(self._h, int(bool(enabled))))
 
     def autotune(self, trial_steps: int = 20):
         """Pick the fastest launch shape; returns ms/step for tile_x 64, 128,

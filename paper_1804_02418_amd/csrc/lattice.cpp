@@ -137,6 +137,7 @@ struct rlbm_lattice {
     int part_blocks = 0;
     double *fref = nullptr, *wscale = nullptr;
     unsigned *gtab = nullptr;  // boundary gather table
+    bool table_off = false;    // rlbm_set_gather_table(0): never build one
     // local-capacitance force: 1/C_g (0: off) and the density ping-pong,
     // nlca[ncur] holding the density of the current state
     double inv_cg = 0.0;
@@ -220,7 +221,8 @@ rlbm_status build_gather_table(rlbm_lattice *L, const std::vector<signed char> &
     // computed gather for huge lattices: table codes are 31-bit element
     // indices, and the kernels that read a table address every population
     // as a 32-bit byte offset from the array
-    if (P * kQ >= (1LL << 31) || P * kQ * (long long)store_bytes(L->storage) >= (1LL << 32)) return RLBM_OK;
+    if (L->table_off || P * kQ >= (1LL << 31) || P * kQ * (long long)store_bytes(L->storage) >= (1LL << 32))
+        return RLBM_OK;
     const int nx = L->nx, ny = L->ny;
     const int w = tuple_width((int)store_bytes(L->storage));
     const bool all = !has_interior(nx, ny, L->mask != nullptr);
@@ -1026,6 +1028,14 @@ rlbm_status rlbm_set_block_order(rlbm_lattice *L, int xcd_contiguous)
     if (xcd_contiguous != 0 && xcd_contiguous != 1) return fail(RLBM_EINVAL, "rlbm_set_block_order: 0 or 1");
     L->shape.xcd = xcd_contiguous;
     return RLBM_OK;
+}
+
+rlbm_status rlbm_set_gather_table(rlbm_lattice *L, int enabled)
+{
+    CHECK_L(L);
+    if (enabled != 0 && enabled != 1) return fail(RLBM_EINVAL, "rlbm_set_gather_table: 0 or 1");
+    L->table_off = enabled == 0;
+    return refresh(L, true);
 }
 
 rlbm_status rlbm_set_streaming_stores(rlbm_lattice *L, int on)

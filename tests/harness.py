@@ -17,10 +17,12 @@ def oracle_lattice(w, use_printed=False):
     return L
 
 
-def gpu_lattice(w, storage=None, shape=None):
+def gpu_lattice(w, storage=None, shape=None, table=True):
     import paper_1804_02418_amd as rl
 
     L = rl.Lattice(w["nx"], w["ny"], storage or w.get("storage", "f64"))
+    if not table:
+        L.set_gather_table(False)
     if w.get("quadrature") is not None:
         L.set_quadrature(*w["quadrature"])
     L.set_boundaries(w["periodic_x"], w["periodic_y"], w["contacts"])

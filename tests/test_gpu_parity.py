@@ -24,9 +24,9 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _compare_run(w, checkpoints, tol=TOL, vscale=None, pops=True):
+def _compare_run(w, checkpoints, tol=TOL, vscale=None, pops=True, table=True):
     O = oracle_lattice(w)
-    G = gpu_lattice(w, "f64")
+    G = gpu_lattice(w, "f64", table=table)
     vs = vscale
     worst = dict(err_n=0.0, err_u=0.0, err_eps=0.0)
     for t in checkpoints:
@@ -104,6 +104,55 @@ def test_smallest_interior_lattices_match_oracle(periodic_x, periodic_y):
                  contacts=[k for k in spans if not (periodic_x and k["edge"] in ("left", "right"))
                            and not (periodic_y and k["edge"] in ("bottom", "top"))])
         _compare_run(w, [0, 1, 12])
+
+
+def _boundary_cases():
+    """Lattices whose boundary rules differ in kind: contacts on every edge
+    (two reaching corners), a masked obstacle (every site through the
+    boundary path), a tiny periodic lattice without interior, the smallest
+    lattice with an interior (periodic along x)."""
+    a = workloads.small_device(nx=150, ny=60, steps=20)
+    c = a["contacts"]
+    a["contacts"] = [dict(c[0], edge="bottom", start=10, width=30), dict(c[2], edge="top", start=100, width=50),
+                     dict(c[3], edge="left", start=0, width=20), dict(c[1], edge="right", start=30, width=30)]
+    b = workloads.small_device(nx=130, ny=50, steps=20)
+    b["periodic_x"] = True
+    b["contacts"] = [k for k in b["contacts"] if k["edge"] in ("bottom", "top")]
+    mask = np.zeros((50, 130), dtype=np.uint8)
+    mask[18:30, 40:47] = 1
+    mask[5:9, 100:128] = 1
+    b["mask"] = mask
+    t = workloads.small_device(nx=3, ny=7, steps=20)
+    t.update(periodic_x=True, periodic_y=True, contacts=[])
+    m = workloads.small_device(nx=11, ny=11, steps=20)
+    m.update(periodic_x=True, contacts=[dict(m["contacts"][0], edge="bottom", start=0, width=11)])
+    return [a, b, t, m]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+def test_in_place_boundary_path_matches_table_path(storage):
+    """Lattices of 4 GiB and more have no gather table: the kernels resolve
+    every boundary source in place (bands and masked lattices through the
+    general gather, side columns with 64-bit addresses).  Forced on small
+    lattices (rlbm_set_gather_table(0)), that path must give the table
+    path's populations and fields bit for bit."""
+    for w in _boundary_cases():
+        A = gpu_lattice(w, storage)
+        B = gpu_lattice(w, storage, table=False)
+        for n in (1, 19):
+            A.step(n)
+            B.step(n)
+        assert np.array_equal(A.read_populations(), B.read_populations()), (w["nx"], w["ny"], storage)
+        fa, fb = A.read_fields(), B.read_fields()
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k]), (w["nx"], w["ny"], storage, k)
+        A.close()
+        B.close()
+
+
+def test_in_place_boundary_path_fp64_matches_oracle():
+    for w in _boundary_cases():
+        _compare_run(w, [0, 1, 20], table=False)
 
 
 @pytest.mark.parametrize("nx,ny", [(1, 6), (3, 7), (5, 2), (70, 3)])

@@ -114,6 +114,7 @@ def test_store_form_and_block_order_reject_bad_arguments():
 
     assert rl.lib().rlbm_set_streaming_stores(None, 1) == _binding.EINVAL
     assert rl.lib().rlbm_set_block_order(None, 0) == _binding.EINVAL
+    assert rl.lib().rlbm_set_gather_table(None, 1) == _binding.EINVAL
 
 
 def test_bandwidth_probe_rejects_bad_arguments():
