@@ -94,6 +94,16 @@ def test_fp32_storage_with_lca():
     _compare(w, [1, 120], storage="f32", tol=(2e-7, 2e-4), pops=False)
 
 
+def test_fp16_storage_with_lca():
+    """FP16 deviation storage (four-shell tuples) with the local-capacitance
+    force, against the FP64 oracle: the bounds of the reduced-storage test
+    in test_gpu_precision.py, set by the float16 rounding of the stored
+    deviation."""
+    w = workloads.small_device(steps=120)
+    w["cg"] = 2.0
+    _compare(w, [1, 120], storage="f16dev", tol=(2e-5, 5e-2), pops=False)
+
+
 def test_infinite_capacitance_is_plain_kernel():
     w = workloads.small_device(nx=96, ny=40, steps=20)
     a = gpu_lattice(w)
