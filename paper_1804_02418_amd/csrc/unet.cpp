@@ -49,6 +49,12 @@ struct rlbm_unet {
     void *wt = nullptr;  // adjoint weights of every 3x3 layer, back to back (adj.toff)
     AdjointTable adj{};
     float *part = nullptr;
+    // per-layer regions for the partial sums of the backward pass, reduced
+    // in one launch at its end (dpart + wpo[i]: weight-gradient chunks,
+    // dpart + bpo[i]: bias rows)
+    float *dpart = nullptr;
+    long long wpo[NLAYER] = {}, bpo[NLAYER] = {};
+    ReduceJobs jobs;
     double *mse_part = nullptr;
     int mse_blocks = 256;
     // activations and their gradients (BF16)
@@ -165,10 +171,18 @@ rlbm_status conv_bwd(rlbm_unet *N, int i, int B, bool want_input)
 {
     const Layer &l = N->L[i];
     const int h = N->lh(l.level), w = N->lw(l.level);
-    UTRY(relu_backward_bias(N->gact[i], N->act[i], N->part, N->grad + l.boff, (long long)B * h * w, l.co,
-                            N->stream));
-    UTRY(conv3x3_backward_weight(N->gact[i], layer_input(N, i), N->part, N->grad + l.woff, B, h, w, l.ci, l.co,
-                                 N->stream));
+    // the partial sums go to the layer's own regions; rlbm_unet_backward
+    // reduces every layer's at its end, in one launch
+    int rows = 0;
+    UTRY(relu_backward_bias_part(N->gact[i], N->act[i], N->dpart + N->bpo[i], N->grad + l.boff,
+                                 (long long)B * h * w, l.co, &rows, N->stream));
+    if (rows > 0 && !add_reduce_job(N->jobs, N->dpart + N->bpo[i], N->grad + l.boff, l.co, rows))
+        return set_error(RLBM_EDEVICE, "rlbm_unet_backward: reduction table full");
+    const int chunks = conv3x3_backward_weight_part(N->gact[i], layer_input(N, i), N->dpart + N->wpo[i], B, h, w,
+                                                    l.ci, l.co, N->stream);
+    if (chunks < 0) return set_error(RLBM_EDEVICE, "rlbm_unet_backward: weight-gradient launch failed");
+    if (!add_reduce_job(N->jobs, N->dpart + N->wpo[i], N->grad + l.woff, (long long)l.co * 9 * l.ci, chunks))
+        return set_error(RLBM_EDEVICE, "rlbm_unet_backward: reduction table full");
     if (want_input) {
         // the adjoint weights of every layer were formed at the start of the
         // backward pass; layer i is entry i (every layer before the head is 3 x 3)
@@ -203,6 +217,7 @@ void rlbm_unet_destroy(rlbm_unet *N)
     ufree(N->theta_bf);
     ufree(N->wt);
     ufree(N->part);
+    ufree(N->dpart);
     ufree(N->mse_part);
     ufree(N->x);
     ufree(N->gx);
@@ -263,12 +278,22 @@ rlbm_status rlbm_unet_create(int base, int cin, int cout, int height, int width,
         N->adj.toff[N->adj.n + 1] = N->adj.toff[N->adj.n] + (long long)l.co * 9 * l.ci;
         ++N->adj.n;
     }
+    long long dpart_len = 0;
     for (int i = 0; i < NLAYER; ++i) {
         const Layer &l = N->L[i];
         const long long np = (long long)px(N, l.level, max_batch);
-        if (l.k == 3)
+        if (l.k == 3) {
             part_max = std::max(part_max, (size_t)conv3x3_wgrad_chunks(max_batch, N->lh(l.level), N->lw(l.level), l.ci, l.co) *
                                               l.co * 9 * l.ci);
+            // the layer's regions hold its partials at any batch up to max_batch
+            int chunks = 1;
+            for (int b = 1; b <= max_batch; ++b)
+                chunks = std::max(chunks, conv3x3_wgrad_chunks(b, N->lh(l.level), N->lw(l.level), l.ci, l.co));
+            N->wpo[i] = dpart_len;
+            dpart_len += (long long)chunks * l.co * 9 * l.ci;
+            N->bpo[i] = dpart_len;
+            dpart_len += (long long)channel_sum_blocks(np) * l.co;
+        }
         // bias sums (and the head's parameter sums): one row per block
         part_max = std::max(part_max, (size_t)channel_sum_blocks(np) * l.co * (l.k == 3 ? 1 : l.ci + 1));
         alloc(&N->act[i], px(N, l.level, max_batch) * l.co * 2);
@@ -276,6 +301,7 @@ rlbm_status rlbm_unet_create(int base, int cin, int cout, int height, int width,
     }
     alloc(&N->wt, (size_t)N->adj.toff[N->adj.n] * 2);
     alloc((void **)&N->part, part_max * 4);
+    alloc((void **)&N->dpart, (size_t)dpart_len * 4);
     alloc((void **)&N->mse_part, N->mse_blocks * 8);
     alloc(&N->x, px(N, 0, max_batch) * cin * 2);
     alloc(&N->gx, px(N, 0, max_batch) * cin * 2);
@@ -425,6 +451,7 @@ rlbm_status rlbm_unet_backward(rlbm_unet *N, const float *dy, int batch, float *
     const int c0 = N->base, c1 = 2 * c0, c2 = 4 * c0, c3 = 8 * c0;
     const Layer &h = N->L[HEAD];
     UTRY(conv3x3_adjoint_weights_all(N->theta_bf, N->wt, N->adj, N->stream));
+    N->jobs = ReduceJobs();
     // the forward read the decoder's concatenations in place; the weight
     // gradients of the decoder's first convolutions want them formed
     UTRY(up_concat(N->act[BB], N->act[E4B], N->cat[3], B, N->lh(3), N->lw(3), c3, c3, N->stream));
@@ -455,6 +482,7 @@ rlbm_status rlbm_unet_backward(rlbm_unet *N, const float *dy, int batch, float *
     if ((st = block(E2A, E2B, true))) return st;
     UTRY(pool_backward(N->gpool[1], N->gcat[0], c1 + c0, c1, N->gact[E1B], B, N->lh(0), N->lw(0), c0, N->stream));
     if ((st = block(E1A, E1B, dx != nullptr))) return st;
+    UTRY(reduce_partials(N->jobs, N->stream));
     if (dx) UTRY(to_f32(N->gx, dx, (long long)px(N, 0, B) * N->cin, N->stream));
     return RLBM_OK;
 }

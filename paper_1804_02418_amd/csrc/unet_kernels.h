@@ -41,6 +41,25 @@ int conv3x3_wgrad_chunks(int B, int H, int W, int Ci, int Co);
 // gw[co][tap][ci] += sum_p dpre[p][co] * in[p + tap][ci] (deterministic two-pass reduction through part).
 hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part, float *gw, int B, int H, int W,
                                    int Ci, int Co, hipStream_t s);
+// The weight-gradient partials alone (the reduction left to reduce_partials);
+// returns the number of chunks written to part, or -1 on a launch error.
+int conv3x3_backward_weight_part(const void *dpre, const void *in, float *part, int B, int H, int W, int Ci, int Co,
+                                 hipStream_t s);
+// Deferred reductions: job j adds sum over c < chunks[j] of
+// part[j][c * len[j] + q] to g[j][q] for q < len[j], in the order of
+// conv3x3_backward_weight's reduction; all jobs in one launch.
+constexpr int kMaxReduceJobs = 48;
+struct ReduceJobs {
+    int n = 0;
+    long long block_start[kMaxReduceJobs + 1] = {};
+    const float *part[kMaxReduceJobs] = {};
+    float *g[kMaxReduceJobs] = {};
+    long long len[kMaxReduceJobs] = {};
+    int chunks[kMaxReduceJobs] = {};
+};
+// Appends a job (false when the table is full).
+bool add_reduce_job(ReduceJobs &j, const float *part, float *g, long long len, int chunks);
+hipError_t reduce_partials(const ReduceJobs &j, hipStream_t s);
 // Blocks of the per-channel and head-gradient sums: part needs
 // channel_sum_blocks(npix) * C floats (head_backward: * O * (C + 1)).
 constexpr int kSumBlocks = 2048;
@@ -53,6 +72,11 @@ hipError_t relu_backward(void *d, const void *out, long long n, hipStream_t s);
 // d *= (out > 0) over npix x C and gb[c] += sum_p d[p][c], in one pass when
 // C % 8 == 0 and C / 8 divides 256 (part as for channel_sum)
 hipError_t relu_backward_bias(void *d, const void *out, float *part, float *gb, long long npix, int C, hipStream_t s);
+// The same with the bias sums left as channel_sum_blocks(npix) rows of C
+// partials in part (for reduce_partials) when C % 8 == 0 and C / 8 divides
+// 256 (*rows = the row count); otherwise as relu_backward_bias (*rows = 0).
+hipError_t relu_backward_bias_part(void *d, const void *out, float *part, float *gb, long long npix, int C, int *rows,
+                                   hipStream_t s);
 hipError_t pool_forward(const void *in, void *out, int B, int H, int W, int C, hipStream_t s);
 // dx = dy / 4 broadcast to 2x2 blocks (+ channels [skip_off, skip_off + C) of skip, a B*H*W*skip_c tensor)
 hipError_t pool_backward(const void *dy, const void *skip, int skip_c, int skip_off, void *dx, int B, int H, int W,

@@ -566,6 +566,42 @@ __global__ __launch_bounds__(256) void reduce_chunks_kernel(const float *__restr
     }
 }
 
+// reduce_chunks_kernel for a table of jobs in one launch: block b belongs to
+// the job whose block range holds it and reduces 16 of that job's outputs
+// exactly as reduce_chunks_kernel does.
+__global__ __launch_bounds__(256) void reduce_jobs_kernel(const ReduceJobs J)
+{
+    const long long b = blockIdx.x;
+    int j = 0;
+    while (j + 1 < J.n && b >= J.block_start[j + 1]) ++j;
+    const float *__restrict__ part = J.part[j];
+    const long long n = J.len[j];
+    const int chunks = J.chunks[j];
+    const int qi = threadIdx.x & 15, grp = threadIdx.x >> 4;
+    const long long q = (b - J.block_start[j]) * 16 + qi;
+    float s = 0.f;
+    if (q < n) {
+        int c = grp;
+        for (; c + 48 < chunks; c += 64) {
+            const float v0 = part[(long long)c * n + q], v1 = part[(long long)(c + 16) * n + q];
+            const float v2 = part[(long long)(c + 32) * n + q], v3 = part[(long long)(c + 48) * n + q];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; c < chunks; c += 16) s += part[(long long)c * n + q];
+    }
+    __shared__ float red[16][16];
+    red[grp][qi] = s;
+    __syncthreads();
+    if (grp == 0 && q < n) {
+        float t = 0.f;
+        for (int k = 0; k < 16; ++k) t += red[k][qi];
+        J.g[j][q] += t;
+    }
+}
+
 // Per-channel sums in two passes (deterministic: fixed partition, fixed
 // order), optionally fused with the ReLU gradient.  Pass 1: block b sums
 // the pixels of its chunk; thread t takes the eight channels 8 (t % G) ..
@@ -1129,12 +1165,12 @@ int conv3x3_wgrad_chunks(int B, int H, int W, int Ci, int Co)
     return B * cpi;
 }
 
-hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part, float *gw, int B, int H, int W,
-                                   int Ci, int Co, hipStream_t s)
+int conv3x3_backward_weight_part(const void *dpre, const void *in, float *part, int B, int H, int W, int Ci, int Co,
+                                 hipStream_t s)
 {
-    if (Ci % 16 || Co % 16 || B < 1 || H < 1 || W < 1) return hipErrorInvalidValue;
+    if (Ci % 16 || Co % 16 || B < 1 || H < 1 || W < 1) return -1;
     // both tensors are addressed with 32-bit byte offsets (buffer loads)
-    if ((long long)B * H * W * (Ci > Co ? Ci : Co) * 2 >= (1LL << 31)) return hipErrorInvalidValue;
+    if ((long long)B * H * W * (Ci > Co ? Ci : Co) * 2 >= (1LL << 31)) return -1;
     int cpi = 0, per = 0;
     wgrad_split(B, H, Ci, Co, cpi, per);
     const int chunks = B * cpi;
@@ -1149,10 +1185,37 @@ hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part
     RLBM_WGRAD(16, 1) RLBM_WGRAD(16, 2) RLBM_WGRAD(16, 4) RLBM_WGRAD(32, 1) RLBM_WGRAD(32, 2) RLBM_WGRAD(32, 4)
     RLBM_WGRAD(64, 1) RLBM_WGRAD(64, 2) RLBM_WGRAD(64, 4)
 #undef RLBM_WGRAD
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError() == hipSuccess ? chunks : -1;
+}
+
+hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part, float *gw, int B, int H, int W,
+                                   int Ci, int Co, hipStream_t s)
+{
+    const int chunks = conv3x3_backward_weight_part(dpre, in, part, B, H, W, Ci, Co, s);
+    if (chunks < 0) return hipErrorInvalidValue;
     const long long n = (long long)Co * 9 * Ci;
     hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, s, part, gw, n, chunks);
+    return hipGetLastError();
+}
+
+bool add_reduce_job(ReduceJobs &j, const float *part, float *g, long long len, int chunks)
+{
+    if (j.n >= kMaxReduceJobs || len < 1 || chunks < 1) return false;
+    j.part[j.n] = part;
+    j.g[j.n] = g;
+    j.len[j.n] = len;
+    j.chunks[j.n] = chunks;
+    j.block_start[j.n + 1] = j.block_start[j.n] + (len + 15) / 16;
+    ++j.n;
+    return true;
+}
+
+hipError_t reduce_partials(const ReduceJobs &j, hipStream_t s)
+{
+    if (j.n == 0) return hipSuccess;
+    const long long blocks = j.block_start[j.n];
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reduce_jobs_kernel, dim3((unsigned)blocks), dim3(256), 0, s, j);
     return hipGetLastError();
 }
 
@@ -1186,6 +1249,20 @@ hipError_t channel_sum(const void *d, float *part, float *gb, long long npix, in
     }
     // no ReLU: the kernel only reads d
     return sum_launch(static_cast<bf16 *>(const_cast<void *>(d)), nullptr, part, gb, npix, C, s);
+}
+
+hipError_t relu_backward_bias_part(void *d, const void *out, float *part, float *gb, long long npix, int C, int *rows,
+                                   hipStream_t s)
+{
+    *rows = 0;
+    if (C < 1 || npix < 1) return hipErrorInvalidValue;
+    if (!fast_sum_shape(C)) return relu_backward_bias(d, out, part, gb, npix, C, s);
+    const int nb = channel_sum_blocks(npix);
+    const long long chunk = (npix + nb - 1) / nb;
+    hipLaunchKernelGGL(channel_sum_part_kernel, dim3(nb), dim3(256), 0, s, static_cast<bf16 *>(d),
+                       static_cast<const bf16 *>(out), part, npix, C, chunk);
+    *rows = nb;
+    return hipGetLastError();
 }
 
 hipError_t relu_backward_bias(void *d, const void *out, float *part, float *gb, long long npix, int C, hipStream_t s)
