@@ -46,8 +46,8 @@ hipError_t conv3x3_backward_weight(const void *dpre, const void *in, float *part
 int conv3x3_backward_weight_part(const void *dpre, const void *in, float *part, int B, int H, int W, int Ci, int Co,
                                  hipStream_t s);
 // Deferred reductions: job j adds sum over c < chunks[j] of
-// part[j][c * len[j] + q] to g[j][q] for q < len[j], in the order of
-// conv3x3_backward_weight's reduction; all jobs in one launch.
+// part[j][c * len[j] + q] to g[j][q] for q < len[j] (a fixed order:
+// deterministic); all jobs in one launch.
 constexpr int kMaxReduceJobs = 48;
 struct ReduceJobs {
     int n = 0;

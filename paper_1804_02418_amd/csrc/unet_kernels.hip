@@ -566,9 +566,11 @@ __global__ __launch_bounds__(256) void reduce_chunks_kernel(const float *__restr
     }
 }
 
-// reduce_chunks_kernel for a table of jobs in one launch: block b belongs to
-// the job whose block range holds it and reduces 16 of that job's outputs
-// exactly as reduce_chunks_kernel does.
+// The deferred reductions of a backward pass in one launch: block b belongs
+// to the job whose block range holds it and sums 64 of that job's outputs
+// over all chunks; wave w takes the chunks c = w (mod 4), four loads in
+// flight, each a 256-byte row segment of one chunk, and the four wave sums
+// are added in wave order (deterministic).
 __global__ __launch_bounds__(256) void reduce_jobs_kernel(const ReduceJobs J)
 {
     const long long b = blockIdx.x;
@@ -577,29 +579,25 @@ __global__ __launch_bounds__(256) void reduce_jobs_kernel(const ReduceJobs J)
     const float *__restrict__ part = J.part[j];
     const long long n = J.len[j];
     const int chunks = J.chunks[j];
-    const int qi = threadIdx.x & 15, grp = threadIdx.x >> 4;
-    const long long q = (b - J.block_start[j]) * 16 + qi;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long long q = (b - J.block_start[j]) * 64 + lane;
     float s = 0.f;
     if (q < n) {
-        int c = grp;
-        for (; c + 48 < chunks; c += 64) {
-            const float v0 = part[(long long)c * n + q], v1 = part[(long long)(c + 16) * n + q];
-            const float v2 = part[(long long)(c + 32) * n + q], v3 = part[(long long)(c + 48) * n + q];
+        int c = w;
+        for (; c + 12 < chunks; c += 16) {
+            const float v0 = part[(long long)c * n + q], v1 = part[(long long)(c + 4) * n + q];
+            const float v2 = part[(long long)(c + 8) * n + q], v3 = part[(long long)(c + 12) * n + q];
             s += v0;
             s += v1;
             s += v2;
             s += v3;
         }
-        for (; c < chunks; c += 16) s += part[(long long)c * n + q];
+        for (; c < chunks; c += 4) s += part[(long long)c * n + q];
     }
-    __shared__ float red[16][16];
-    red[grp][qi] = s;
+    __shared__ float red[4][64];
+    red[w][lane] = s;
     __syncthreads();
-    if (grp == 0 && q < n) {
-        float t = 0.f;
-        for (int k = 0; k < 16; ++k) t += red[k][qi];
-        J.g[j][q] += t;
-    }
+    if (w == 0 && q < n) J.g[j][q] += ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // Per-channel sums in two passes (deterministic: fixed partition, fixed
@@ -1205,7 +1203,7 @@ bool add_reduce_job(ReduceJobs &j, const float *part, float *g, long long len, i
     j.g[j.n] = g;
     j.len[j.n] = len;
     j.chunks[j.n] = chunks;
-    j.block_start[j.n + 1] = j.block_start[j.n] + (len + 15) / 16;
+    j.block_start[j.n + 1] = j.block_start[j.n] + (len + 63) / 64;
     ++j.n;
     return true;
 }
