@@ -1339,7 +1339,10 @@ hipError_t head_backward(const float *dy, const void *x, const void *w, void *dx
                            gb, npix, C, O);
         return hipGetLastError();
     }
-    const int nb = channel_sum_blocks(npix);
+    // at most 256 blocks (at least eight pixels per thread at 256 x 256 x 8):
+    // each block ends in a reduction of its 51 sums, which one pixel per
+    // thread would leave as the kernel's main cost
+    const int nb = channel_sum_blocks(npix) < 256 ? channel_sum_blocks(npix) : 256;
     const long long chunk = (npix + nb - 1) / nb;
     hipLaunchKernelGGL((head_wgrad_part_kernel<16, 3>), dim3(nb), dim3(256), 0, s, dy, static_cast<const bf16 *>(x),
                        part, npix, chunk);
