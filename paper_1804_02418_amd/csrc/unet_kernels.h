@@ -62,7 +62,7 @@ bool add_reduce_job(ReduceJobs &j, const float *part, float *g, long long len, i
 hipError_t reduce_partials(const ReduceJobs &j, hipStream_t s);
 // Blocks of the per-channel and head-gradient sums: part needs
 // channel_sum_blocks(npix) * C floats (head_backward: * O * (C + 1)).
-constexpr int kSumBlocks = 2048;
+constexpr int kSumBlocks = 512;
 int channel_sum_blocks(long long npix);
 // gb[c] += sum_p d[p][c] (deterministic two-pass sum through part when C
 // divides 256, one block per channel otherwise)
