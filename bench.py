@@ -635,7 +635,7 @@ def main(argv=None):
 
         for st in ("f64", "f32", "f16dev"):
             if st != args.storage:
-                variant(w, st, 500, 50)
+                variant(w, st, 2000, 100)
         small = workloads.graphene_sample(1024, 512)
         for st in ("f64", "f32", "f16dev"):
             variant(small, st, 4000, 200)
