@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -42,10 +43,16 @@ KERNEL_SOURCES = ["paper_1804_02418_amd/csrc/step_impl.h", "paper_1804_02418_amd
 
 
 def kernel_source_sha() -> str:
+    """Hash of the step kernel's code (comments and blank lines left out, so
+    that a comment edit does not orphan the counter records taken on it)."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(HERE, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, p), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        lines = [ln.rstrip() for ln in text.splitlines() if ln.strip()]
+        h.update("\n".join(lines).encode())
     return h.hexdigest()[:16]
 
 

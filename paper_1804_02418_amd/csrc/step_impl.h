@@ -1,7 +1,8 @@
 // gfx950 kernels of the fused relativistic LB step (templates; each
 // storage is instantiated in a translation unit of its own).
 //
-// Storage: 48 SoA planes of nx*ny values, plane i = population i = 4*d + j,
+// Storage: 48 SoA planes of nx*ny values, plane i = population i = 4*d + j
+// (float16: 12 arrays of four-shell direction tuples, see tuple_width),
 // holding the post-collision state f*(t) as the scaled deviation eta_i from
 // the reference rest equilibrium.  One step reads f*(t) from src and writes
 // f*(t+1) to dst (ping-pong), so every stored value is read exactly once
@@ -9,10 +10,11 @@
 //
 // Work mapping: one thread per site; a block covers tile_x consecutive
 // sites of `rows` rows, so each wavefront reads 64 consecutive values of a
-// plane row (shifted by the hop) and writes 64 aligned values.  Blocks whose
+// plane row (shifted by the hop) and writes 64 aligned values.  Waves whose
 // 5-site halo lies inside the lattice (and without a solid mask) take a
 // branch-free gather; the others resolve periodic wrap, contact ghost spans
-// and bounce-back per population.
+// and bounce-back per lane (side columns and the top and bottom bands), or
+// through a host-built table (lattices with a solid mask).
 #pragma once
 
 #include "rlbm_kernels.h"
@@ -540,19 +542,22 @@ __device__ __forceinline__ void side_wave_gather(const StepArgs<R> &A, const S *
 }
 
 // One block of a time step.  The step's 1-D grid of 256-thread blocks: the
-// first nbnd blocks take the boundary sites (gather table or computed
-// gather), the rest tile the rows y in [5, ny - 5) over their whole width
-// with tile_x * rows sites per block, tiles aligned to tile_x so every
-// wavefront stores 64 aligned values; the side columns of those rows patch
-// their boundary populations in place (side_gather).
+// first nbnd blocks take the boundary sites (the top and bottom bands,
+// band_wave_gather; every site through the gather table, or the computed
+// gather without one, when the lattice has a mask or no interior), the rest
+// tile the rows y in [5, ny - 5) over their whole width with tile_x * rows
+// sites per block, tiles aligned to tile_x so every wavefront stores 64
+// aligned values; the side columns of those rows patch their boundary
+// populations in place (side_wave_gather).
 // Force mode of a step kernel, fixed at compile time so that no runtime
 // branch splits the register allocation: no force, the uniform drive, or
 // the drive plus the local-capacitance term.
 enum ForceMode { kNoForce = 0, kDrive = 1, kLca = 2 };
 
-// GATHER: kGatherTable (the boundary band always has a gather table),
-// kGatherComputed (it never has: huge lattices) or kGatherEither (decided
-// per launch from the arguments; the batched kernel).  The computed gather
+// GATHER: kGatherTable (the lattice has a gather table: its population
+// array is below 4 GiB), kGatherComputed (it has none: 4 GiB and more, or
+// dropped with rlbm_set_gather_table) or kGatherEither (decided per launch
+// from the arguments; the batched kernel).  The computed gather
 // is long code, kept out of the kernels that do not need it.
 enum GatherMode { kGatherTable = 0, kGatherComputed = 1, kGatherEither = 2 };
 
