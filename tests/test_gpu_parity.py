@@ -150,6 +150,25 @@ def test_in_place_boundary_path_matches_table_path(storage):
         B.close()
 
 
+@pytest.mark.parametrize("storage,tol_n,tol_u", [("f32", 2e-7, 2e-4), ("f16dev", 2e-5, 5e-2)])
+def test_reduced_storage_boundary_cases_match_oracle(storage, tol_n, tol_u):
+    """FP32 and FP16 storage (the latter in four-shell tuples) on every kind
+    of boundary, against the FP64 oracle: the bounds of the reduced-storage
+    test in test_gpu_precision.py (the rounding of the stored deviation)."""
+    for w in _boundary_cases():
+        O = oracle_lattice(w)
+        G = gpu_lattice(w, storage)
+        for t in (1, 20):
+            O.run(t - O.t)
+            G.step(t - G.time)
+            ref = O.fields()
+            vs = float(np.max(np.hypot(ref["vx"], ref["vy"]))) or 1.0
+            e = field_errors(G.read_fields(), ref, vscale=vs, mask=w.get("mask"))
+            _say(w["name"], storage, "t", t, e)
+            assert e["err_n"] <= tol_n and e["err_u"] <= tol_u, (w["nx"], w["ny"], t, e)
+        G.close()
+
+
 def test_in_place_boundary_path_fp64_matches_oracle():
     for w in _boundary_cases():
         _compare_run(w, [0, 1, 20], table=False)
