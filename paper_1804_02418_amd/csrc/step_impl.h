@@ -722,7 +722,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, sizeof(S
 // live across iterations and needs every register of the SIMD, one wave
 // per SIMD; one item per block keeps the single-lattice kernel's budget.)
 template <class S, class R, bool NT>
-__global__ __launch_bounds__(256) void batch_step_kernel(const BatchDesc<R> *__restrict__ descs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, sizeof(S) == 2 ? 5 : 4))) void batch_step_kernel(const BatchDesc<R> *__restrict__ descs,
                                                          const unsigned *__restrict__ items,
                                                          const int *__restrict__ n_items_p, int parity, int wf,
                                                          int xcd)
