@@ -84,14 +84,21 @@ def make_lattice(w, storage, stream):
 def run_gpu(w, storage, steps, warmup, autotune=True):
     """Returns (seconds for `steps` steps, average launch ms, residual)
     timed with HIP events on the lattice's stream (torch's current stream).
-    The library's autotuner picks the launch shape first (its trials are
-    rolled back, so the timed steps start from the same state)."""
+    The library's autotuner picks the launch shape and memory form first
+    (its trials are rolled back, so the timed steps start from the same
+    state); the pick is left in run_gpu.launch."""
     import torch
 
     stream = torch.cuda.current_stream()
     L = make_lattice(w, storage, stream.cuda_stream)
+    launch = None
     if autotune:
-        L.autotune(10)
+        # about 50 M site updates per candidate (10 steps at 4096 x 2048,
+        # 95 at 1024 x 512), so that small lattices are not timed on noise
+        ms = L.autotune(max(10, 50_000_000 // (w["nx"] * w["ny"])))
+        c = int(np.where(ms > 0, ms, np.inf).argmin())
+        launch = {"tile_x": (64, 128, 256)[c % 3], "streaming_stores": bool(c // 3 & 1),
+                  "nontemporal_loads": bool(c // 3 & 2)}
     L.step(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -107,6 +114,7 @@ def run_gpu(w, storage, steps, warmup, autotune=True):
     except Exception as exc:  # health check failure is reported, not hidden
         r = f"unstable: {exc}"
     L.close()
+    run_gpu.launch = launch
     return ms / 1e3, ms / max(steps, 1), r
 
 
@@ -621,6 +629,7 @@ def main(argv=None):
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": measured_traffic(f"step_{args.storage}_{w['nx']}x{w['ny']}", sites)},
         "residual_last_call": resid,
+        "launch": run_gpu.launch,
     }
     print(f"headline {mlups:.1f} MLUPS, {achieved / PEAK_HBM_GBS:.4f} of HBM peak", file=sys.stderr, flush=True)
     if args.sustained_steps > 0:
@@ -638,7 +647,8 @@ def main(argv=None):
             gbs = 2 * 48 * BYTES_PER_POP[st] * n / (l3 / 1e3) / 1e9
             extra[f"{wv['name']}_{st}"] = {"mlups": round(n * steps / s3 / 1e6, 1), "hbm_gbs": round(gbs, 1),
                                            "frac": round(gbs / PEAK_HBM_GBS, 4),
-                                           "cache_resident": cache_resident(wv, st), "steps": steps}
+                                           "cache_resident": cache_resident(wv, st), "steps": steps,
+                                           "launch": run_gpu.launch}
 
         for st in ("f64", "f32", "f16dev"):
             if st != args.storage:

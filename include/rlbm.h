@@ -88,7 +88,8 @@ typedef struct {
 /* Message of the last failed call on this thread ("" if none). */
 const char *rlbm_last_error(void);
 
-/* ABI version (incremented on incompatible changes). */
+/* ABI version (incremented on incompatible changes): 2 (the autotuner
+ * reports 12 timings). */
 int rlbm_version(void);
 
 /* The quadrature the library uses (Sec. 2.3): the printed weights w_1j
@@ -272,17 +273,29 @@ rlbm_status rlbm_set_gather_table(rlbm_lattice *lat, int enabled);
  * active sample has it on. */
 rlbm_status rlbm_set_streaming_stores(rlbm_lattice *lat, int on);
 
+/* Non-temporal population loads: on = 1 launches the form of the step
+ * kernel whose interior loads do not allocate in the caches, which leaves
+ * the Infinity Cache to the populations the step stores (the next step's
+ * input).  Pays off where one population array fits the 256 MB cache but
+ * the two do not (FP64 at 1024 x 512: 9% faster with ordinary stores);
+ * elsewhere it is slower (2-14% on the graphene sample).  Off by default; the
+ * autotuner decides.  Results are identical either way.  Batches always use
+ * ordinary loads.  Any nonzero on counts as 1. */
+rlbm_status rlbm_set_streaming_loads(rlbm_lattice *lat, int on);
+
 /* Autotuner: time every candidate launch shape of the step kernel on this
- * lattice -- tile_x 64, 128, 256, each with ordinary and with streaming
- * stores -- (trial_steps timed steps each, after 2 warm-up steps, with HIP
- * events on the lattice's stream), keep the fastest, and remember it for
+ * lattice -- tile_x 64, 128, 256, each in four memory forms: ordinary
+ * loads and stores, streaming stores, non-temporal loads, both --
+ * (trial_steps timed steps each, after 2 warm-up steps, with HIP events on
+ * the lattice's stream), keep the fastest, and remember it for
  * lattices of the same device architecture, storage, size and mask use in
  * this process (and in the text file named by the environment variable
  * RLBM_TUNE_CACHE, if set, which later processes read at rlbm_create).  The
  * lattice state, time and fields are restored afterwards.  ms_per_step
- * (optional, 6 entries, caller-owned) receives the timings of tile_x = 64,
- * 128, 256 with ordinary stores, then the same with streaming stores (0 for
- * a shape that does not apply).  Synchronises. */
+ * (optional, 12 entries since ABI version 2, caller-owned) receives the
+ * timings of tile_x = 64, 128, 256 in the ordinary form, then the same with
+ * streaming stores, with non-temporal loads, and with both (0 for a shape
+ * that does not apply).  Synchronises. */
 rlbm_status rlbm_autotune(rlbm_lattice *lat, int trial_steps, double *ms_per_step);
 
 /* Block until all work queued on the lattice's stream is done. */

@@ -9,6 +9,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librlbm.so")
+ABI_VERSION = 2
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EUNSTABLE, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 F64, F32, F16DEV = 0, 1, 2
@@ -92,6 +93,7 @@ SIGNATURES = {
     "rlbm_get_launch_shape": ([_vp, _ip, _ip], None),
     "rlbm_autotune": ([_vp, ctypes.c_int, _dp], None),
     "rlbm_set_streaming_stores": ([_vp, ctypes.c_int], None),
+    "rlbm_set_streaming_loads": ([_vp, ctypes.c_int], None),
     "rlbm_set_gather_table": ([_vp, ctypes.c_int], None),
     "rlbm_synchronize": ([_vp], None),
     "rlbm_batch_create": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)], None),
@@ -143,6 +145,8 @@ def lib() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = None if res == "void" else (ctypes.c_int if res is None else res)
+        if L.rlbm_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI version {L.rlbm_version()}, this binding {ABI_VERSION}: rebuild it")
         _lib = L
     return _lib
 
@@ -342,15 +346,19 @@ class Lattice:
     def set_streaming_stores(self, on: bool):
         check(lib().rlbm_set_streaming_stores(self._h, int(bool(on))))
 
+    def set_streaming_loads(self, on: bool):
+        check(lib().rlbm_set_streaming_loads(self._h, int(bool(on))))
+
     def set_gather_table(self, enabled: bool):
         """False: resolve every boundary source in place, as lattices of 4 GiB
         and more do (include/rlbm.h)."""
         check(lib().rlbm_set_gather_table(self._h, int(bool(enabled))))
 
     def autotune(self, trial_steps: int = 20):
-        """Pick the fastest launch shape; returns ms/step for tile_x 64, 128,
-        256 with ordinary stores, then with streaming stores."""
-        ms = np.zeros(6)
+        """Pick the fastest launch shape and memory form; returns ms/step for
+        tile_x 64, 128, 256 in the ordinary form, then with streaming stores,
+        with non-temporal loads, and with both."""
+        ms = np.zeros(12)
         check(lib().rlbm_autotune(self._h, int(trial_steps), ms.ctypes.data_as(_dp)))
         return ms
 

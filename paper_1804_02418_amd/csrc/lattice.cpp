@@ -126,6 +126,7 @@ struct rlbm_lattice {
     int cur = 0;
     LaunchShape shape{256, 1};
     int nt_store = 0;  // streaming (non-temporal) population stores
+    int nt_load = 0;   // non-temporal interior population loads
     // device buffers
     void *pop[2] = {nullptr, nullptr};
     double *fld = nullptr;   // 4 planes: n, vx, vy, eps
@@ -167,6 +168,7 @@ void fill_args(rlbm_lattice *L, StepArgs<R> &A)
     A.has_force = (L->Fx != 0.0 || L->Fy != 0.0);
     A.write_fields = 0;
     A.nt_store = L->nt_store;
+    A.nt_load = L->nt_load;
     A.plane = L->plane();
     for (int j = 0; j < kShells; ++j) {
         A.wp0[0][j] = R(L->scale * q.w1[j] * q.p0[j]);
@@ -313,16 +315,29 @@ rlbm_status refresh(rlbm_lattice *L, bool geometry)
     return RLBM_OK;
 }
 
+// bit 0: streaming stores, bit 1: non-temporal interior loads
+void set_memory_form(rlbm_lattice *L, int form)
+{
+    L->nt_store = form & 1;
+    L->nt_load = (form >> 1) & 1;
+    L->args_d.nt_store = L->args_f.nt_store = L->nt_store;
+    L->args_d.nt_load = L->args_f.nt_load = L->nt_load;
+}
+
 void set_write_fields(rlbm_lattice *L, int on)
 {
     L->args_d.write_fields = on;
     L->args_f.write_fields = on;
 }
 
-// ---- autotune cache: (arch, storage, nx, ny, mask) -> tile_x ----
+// ---- autotune cache: (arch, storage, nx, ny, mask) -> tile_x and memory
+// form (bit 0: streaming stores, bit 1: non-temporal loads) ----
 using TuneKey = std::tuple<std::string, int, int, int, int>;
+struct TuneVal {
+    int tile_x, form;
+};
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune;
+std::map<TuneKey, TuneVal> g_tune;
 bool g_tune_loaded = false;
 
 std::string device_arch()
@@ -343,22 +358,27 @@ void tune_cache_load()
     if (!path) return;
     FILE *f = std::fopen(path, "r");
     if (!f) return;
-    char arch[64];
-    int st, nx, ny, mask, tile;
-    while (std::fscanf(f, "%63s %d %d %d %d %d", arch, &st, &nx, &ny, &mask, &tile) == 6)
-        g_tune[TuneKey(arch, st, nx, ny, mask)] = tile;
+    // one entry per line: arch storage nx ny mask tile_x form; lines of
+    // another shape or with values out of range are skipped
+    char line[256], arch[64];
+    int st, nx, ny, mask, tile, form;
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::sscanf(line, "%63s %d %d %d %d %d %d", arch, &st, &nx, &ny, &mask, &tile, &form) != 7) continue;
+        if ((tile != 64 && tile != 128 && tile != 256) || form < 0 || form > 3) continue;
+        g_tune[TuneKey(arch, st, nx, ny, mask)] = TuneVal{tile, form};
+    }
     std::fclose(f);
 }
 
-void tune_cache_store(const TuneKey &k, int tile)
+void tune_cache_store(const TuneKey &k, TuneVal v)
 {
-    g_tune[k] = tile;
+    g_tune[k] = v;
     const char *path = std::getenv("RLBM_TUNE_CACHE");
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d %d\n", std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k), std::get<3>(k),
-                 std::get<4>(k), tile);
+    std::fprintf(f, "%s %d %d %d %d %d %d\n", std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                 std::get<4>(k), v.tile_x, v.form);
     std::fclose(f);
 }
 
@@ -377,7 +397,7 @@ extern "C" {
 
 const char *rlbm_last_error(void) { return g_error.c_str(); }
 
-int rlbm_version(void) { return 1; }
+int rlbm_version(void) { return 2; }
 
 rlbm_status rlbm_quadrature(double w1[4], double w2[4], double p0[4])
 {
@@ -459,8 +479,9 @@ rlbm_status rlbm_create(int nx, int ny, rlbm_storage storage, void *hip_stream, 
         tune_cache_load();
         auto it = g_tune.find(TuneKey(device_arch(), (int)storage, nx, ny, 0));
         if (it != g_tune.end()) {
-            L->shape = LaunchShape{it->second / 2, 256 / (it->second / 2)};
-            L->nt_store = it->second & 1;
+            L->shape = LaunchShape{it->second.tile_x, 256 / it->second.tile_x};
+            L->nt_store = it->second.form & 1;
+            L->nt_load = (it->second.form >> 1) & 1;
         }
     }
     const size_t P = (size_t)nx * ny;
@@ -964,15 +985,17 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
     if (e == hipSuccess) e = hipEventCreate(&e1);
     const int tiles[3] = {64, 128, 256};
     double best = INFINITY;
-    int best_tile = shape0.tile_x, best_nt = L->nt_store;
-    const int nt0 = L->nt_store;
+    const int form0 = L->nt_store | (L->nt_load << 1);
+    int best_tile = shape0.tile_x, best_form = form0;
     const int interior_w = L->nx;  // interior tiles span whole rows
-    for (int c = 0; c < 6 && e == hipSuccess; ++c) {
-        const int tc = c % 3, nt = c / 3;
+    // candidate c: tile tiles[c % 3], memory form c / 3 (bit 0: streaming
+    // stores, bit 1: non-temporal loads)
+    for (int c = 0; c < 12 && e == hipSuccess; ++c) {
+        const int tc = c % 3, form = c / 3;
         if (ms_per_step) ms_per_step[c] = 0.0;
         if (tc > 0 && tiles[tc - 1] >= interior_w) continue;  // wider tiles only add idle lanes
         L->shape = LaunchShape{tiles[tc], 256 / tiles[tc], shape0.xcd};
-        rlbm_set_streaming_stores(L, nt);
+        set_memory_form(L, form);
         rlbm_status st = rlbm_step(L, 2);
         if (st == RLBM_OK) e = hipEventRecord(e0, L->stream);
         if (st == RLBM_OK && e == hipSuccess) st = rlbm_step(L, trial_steps);
@@ -985,11 +1008,11 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
             break;
         }
         const double per = ms / trial_steps;
-        if (ms_per_step && c >= 0) ms_per_step[c] = per;
+        if (ms_per_step) ms_per_step[c] = per;
         if (per < best) {
             best = per;
             best_tile = tiles[tc];
-            best_nt = nt;
+            best_form = form;
         }
     }
     // restore
@@ -1012,13 +1035,14 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
     L->fields_valid = fv0;
     if (e != hipSuccess) {
         L->shape = shape0;
-        rlbm_set_streaming_stores(L, nt0);
+        set_memory_form(L, form0);
         return fail(RLBM_EDEVICE, "rlbm_autotune: %s", hipGetErrorString(e));
     }
     L->shape = LaunchShape{best_tile, 256 / best_tile, shape0.xcd};
-    rlbm_set_streaming_stores(L, best_nt);
+    set_memory_form(L, best_form);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    tune_cache_store(TuneKey(device_arch(), (int)L->storage, L->nx, L->ny, L->mask ? 1 : 0), 2 * best_tile + best_nt);
+    tune_cache_store(TuneKey(device_arch(), (int)L->storage, L->nx, L->ny, L->mask ? 1 : 0),
+                     TuneVal{best_tile, best_form});
     return RLBM_OK;
 }
 
@@ -1041,9 +1065,14 @@ rlbm_status rlbm_set_gather_table(rlbm_lattice *L, int enabled)
 rlbm_status rlbm_set_streaming_stores(rlbm_lattice *L, int on)
 {
     CHECK_L(L);
-    L->nt_store = on ? 1 : 0;
-    L->args_d.nt_store = L->nt_store;
-    L->args_f.nt_store = L->nt_store;
+    set_memory_form(L, (on ? 1 : 0) | (L->nt_load << 1));
+    return RLBM_OK;
+}
+
+rlbm_status rlbm_set_streaming_loads(rlbm_lattice *L, int on)
+{
+    CHECK_L(L);
+    set_memory_form(L, L->nt_store | ((on ? 1 : 0) << 1));
     return RLBM_OK;
 }
 

@@ -113,6 +113,7 @@ struct StepArgs {
     int has_force;
     int write_fields;
     int nt_store;     // 1: stores bypass the caches (streaming), 0: ordinary stores
+    int nt_load;      // 1: interior population loads are non-temporal (no cache allocation)
     long long plane;  // nx * ny
     // moments of eta: N^a = N_ref^a + sum_i wp0 * eta_i * (1, nhat), T likewise with wp0sq
     R wp0[2][kShells];    // scale * w_gj * p0_j

@@ -352,6 +352,27 @@ def test_bandwidth_probe_runs_every_pattern():
             assert np.isfinite(g) and g > 0 and u > 0, (pattern, elem, nt, g, u)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
+def test_memory_forms_agree(storage):
+    """Streaming stores and non-temporal loads, alone or together, give
+    bit-identical populations (they change only how the caches are used)."""
+    w = workloads.small_device(nx=300, ny=33, steps=5)
+    ref = gpu_lattice(w, storage)
+    ref.set_streaming_stores(False)
+    ref.set_streaming_loads(False)
+    ref.step(5)
+    a = ref.read_populations()
+    for nt_store, nt_load in ((True, False), (False, True), (True, True)):
+        _say(f"memory form {storage} stores={nt_store} loads={nt_load}")
+        G = gpu_lattice(w, storage)
+        G.set_streaming_stores(nt_store)
+        G.set_streaming_loads(nt_load)
+        G.step(5)
+        assert np.array_equal(a, G.read_populations()), (nt_store, nt_load)
+        G.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("shape", [(64, 4), (128, 2), (256, 1)])
 @pytest.mark.parametrize("xcd", [False, True])
 def test_launch_shapes_agree(shape, xcd):
