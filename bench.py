@@ -93,9 +93,9 @@ def run_gpu(w, storage, steps, warmup, autotune=True):
     L = make_lattice(w, storage, stream.cuda_stream)
     launch = None
     if autotune:
-        # about 50 M site updates per candidate (10 steps at 4096 x 2048,
-        # 95 at 1024 x 512), so that small lattices are not timed on noise
-        ms = L.autotune(max(10, 50_000_000 // (w["nx"] * w["ny"])))
+        # about 100 M site updates per candidate run (12 steps at 4096 x 2048,
+        # 190 at 1024 x 512), so that small lattices are not timed on noise
+        ms = L.autotune(max(10, 100_000_000 // (w["nx"] * w["ny"])))
         c = int(np.where(ms > 0, ms, np.inf).argmin())
         launch = {"tile_x": (64, 128, 256)[c % 3], "streaming_stores": bool(c // 3 & 1),
                   "nontemporal_loads": bool(c // 3 & 2)}

@@ -278,7 +278,7 @@ rlbm_status rlbm_set_streaming_stores(rlbm_lattice *lat, int on);
  * the Infinity Cache to the populations the step stores (the next step's
  * input).  Pays off where one population array fits the 256 MB cache but
  * the two do not (FP64 at 1024 x 512: 9% faster with ordinary stores);
- * elsewhere it is slower (2-14% on the graphene sample).  Off by default; the
+ * elsewhere it is slower (3-14% on the graphene sample).  Off by default; the
  * autotuner decides.  Results are identical either way.  Batches always use
  * ordinary loads.  Any nonzero on counts as 1. */
 rlbm_status rlbm_set_streaming_loads(rlbm_lattice *lat, int on);
@@ -286,14 +286,16 @@ rlbm_status rlbm_set_streaming_loads(rlbm_lattice *lat, int on);
 /* Autotuner: time every candidate launch shape of the step kernel on this
  * lattice -- tile_x 64, 128, 256, each in four memory forms: ordinary
  * loads and stores, streaming stores, non-temporal loads, both --
- * (trial_steps timed steps each, after 2 warm-up steps, with HIP events on
- * the lattice's stream), keep the fastest, and remember it for
+ * (two rounds, the second in the reverse order, each candidate timed over
+ * trial_steps steps after 2 warm-up steps with HIP events on the lattice's
+ * stream and keeping the faster of its two runs), keep the fastest, and
+ * remember it for
  * lattices of the same device architecture, storage, size and mask use in
  * this process (and in the text file named by the environment variable
  * RLBM_TUNE_CACHE, if set, which later processes read at rlbm_create).  The
  * lattice state, time and fields are restored afterwards.  ms_per_step
- * (optional, 12 entries since ABI version 2, caller-owned) receives the
- * timings of tile_x = 64, 128, 256 in the ordinary form, then the same with
+ * (optional, 12 entries since ABI version 2, caller-owned) receives those
+ * timings for tile_x = 64, 128, 256 in the ordinary form, then the same with
  * streaming stores, with non-temporal loads, and with both (0 for a shape
  * that does not apply).  Synchronises. */
 rlbm_status rlbm_autotune(rlbm_lattice *lat, int trial_steps, double *ms_per_step);
