@@ -95,10 +95,9 @@ def run_gpu(w, storage, steps, warmup, autotune=True):
     if autotune:
         # about 100 M site updates per candidate run (12 steps at 4096 x 2048,
         # 190 at 1024 x 512), so that small lattices are not timed on noise
-        ms = L.autotune(max(10, 100_000_000 // (w["nx"] * w["ny"])))
-        c = int(np.where(ms > 0, ms, np.inf).argmin())
-        launch = {"tile_x": (64, 128, 256)[c % 3], "streaming_stores": bool(c // 3 & 1),
-                  "nontemporal_loads": bool(c // 3 & 2)}
+        L.autotune(max(10, 100_000_000 // (w["nx"] * w["ny"])))
+        nts, ntl = L.memory_form()
+        launch = {"tile_x": L.launch_shape()[0], "streaming_stores": nts, "nontemporal_loads": ntl}
     L.step(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)

@@ -283,6 +283,11 @@ rlbm_status rlbm_set_streaming_stores(rlbm_lattice *lat, int on);
  * ordinary loads.  Any nonzero on counts as 1. */
 rlbm_status rlbm_set_streaming_loads(rlbm_lattice *lat, int on);
 
+/* The memory form the next step launches with (as set, autotuned or read
+ * from the tune cache at rlbm_create): *streaming_stores and
+ * *nontemporal_loads receive 0 or 1; either pointer may be NULL. */
+rlbm_status rlbm_get_memory_form(rlbm_lattice *lat, int *streaming_stores, int *nontemporal_loads);
+
 /* Autotuner: time every candidate launch shape of the step kernel on this
  * lattice -- tile_x 64, 128, 256, each in four memory forms: ordinary
  * loads and stores, streaming stores, non-temporal loads, both --

@@ -94,6 +94,7 @@ SIGNATURES = {
     "rlbm_autotune": ([_vp, ctypes.c_int, _dp], None),
     "rlbm_set_streaming_stores": ([_vp, ctypes.c_int], None),
     "rlbm_set_streaming_loads": ([_vp, ctypes.c_int], None),
+    "rlbm_get_memory_form": ([_vp, _ip, _ip], None),
     "rlbm_set_gather_table": ([_vp, ctypes.c_int], None),
     "rlbm_synchronize": ([_vp], None),
     "rlbm_batch_create": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.POINTER(_vp)], None),
@@ -348,6 +349,12 @@ class Lattice:
 
     def set_streaming_loads(self, on: bool):
         check(lib().rlbm_set_streaming_loads(self._h, int(bool(on))))
+
+    def memory_form(self):
+        """(streaming stores, non-temporal loads) of the next step."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        check(lib().rlbm_get_memory_form(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return bool(a.value), bool(b.value)
 
     def set_gather_table(self, enabled: bool):
         """False: resolve every boundary source in place, as lattices of 4 GiB

@@ -1083,6 +1083,14 @@ rlbm_status rlbm_set_streaming_loads(rlbm_lattice *L, int on)
     return RLBM_OK;
 }
 
+rlbm_status rlbm_get_memory_form(rlbm_lattice *L, int *streaming_stores, int *nontemporal_loads)
+{
+    CHECK_L(L);
+    if (streaming_stores) *streaming_stores = L->nt_store;
+    if (nontemporal_loads) *nontemporal_loads = L->nt_load;
+    return RLBM_OK;
+}
+
 rlbm_status rlbm_synchronize(rlbm_lattice *L)
 {
     CHECK_L(L);

@@ -114,6 +114,7 @@ def test_store_form_and_block_order_reject_bad_arguments():
 
     assert rl.lib().rlbm_set_streaming_stores(None, 1) == _binding.EINVAL
     assert rl.lib().rlbm_set_streaming_loads(None, 1) == _binding.EINVAL
+    assert rl.lib().rlbm_get_memory_form(None, None, None) == _binding.EINVAL
     assert rl.lib().rlbm_version() == _binding.ABI_VERSION
     assert rl.lib().rlbm_set_block_order(None, 0) == _binding.EINVAL
     assert rl.lib().rlbm_set_gather_table(None, 1) == _binding.EINVAL
