@@ -215,6 +215,37 @@ def test_graphene_sample_full_size_one_step_from_gpu_state():
     G.close()
 
 
+def test_population_array_beyond_4gib_one_step_from_gpu_state():
+    """The largest class of lattice: a population array of 4 GiB and more
+    (FP64 4096 x 2816, 11.5 M sites, 4.43 GB per array) has no gather table,
+    and the kernels resolve every boundary source in place, with 64-bit
+    addresses, at the real size.  After 50 GPU steps the oracle streams and
+    collides the GPU's own post-collision state; the GPU's next step must
+    agree at every site."""
+    import oracle
+
+    w = workloads.graphene_sample(4096, 2816, storage="f64")
+    assert w["nx"] * w["ny"] * 48 * 8 >= 1 << 32
+    G = gpu_lattice(w, "f64")
+    G.step(50)
+    fstar = G.read_populations()
+    G.step(1)
+    got_f = G.read_populations()
+    got = G.read_fields()
+    G.close()
+    O = oracle_lattice(w)
+    fpre = np.empty_like(fstar)
+    oracle.lib().orc_lattice_stream(O._h, oracle._ptr(np.ascontiguousarray(fstar)), oracle._ptr(fpre))
+    del fstar
+    O.f = fpre
+    ref = O.fields()
+    exp_f = O.post_collision()
+    e = field_errors(got, ref)
+    perr = float(np.abs(got_f - exp_f).max() / np.abs(exp_f).max())
+    _say("4096x2816 (array beyond 4 GiB) one step", e, "populations", perr)
+    assert e["err_n"] <= TOL and e["err_u"] <= TOL and perr <= TOL
+
+
 def test_graphene_sample_full_size_200_steps_matches_oracle():
     """1024 x 512 graphene sample, FP64, 200 steps on both sides from the
     uniform start, every site.  n and eps hold 1e-12 relative.  The velocity
