@@ -93,11 +93,12 @@ def run_gpu(w, storage, steps, warmup, autotune=True):
     L = make_lattice(w, storage, stream.cuda_stream)
     launch = None
     if autotune:
-        # about 100 M site updates per candidate run (12 steps at 4096 x 2048,
-        # 190 at 1024 x 512), so that small lattices are not timed on noise
-        L.autotune(max(10, 100_000_000 // (w["nx"] * w["ny"])))
+        # about 300 M site updates per candidate run (35 steps at 4096 x 2048,
+        # 572 at 1024 x 512), so that small lattices are not timed on noise
+        ms = L.autotune(max(10, 300_000_000 // (w["nx"] * w["ny"])))
         nts, ntl = L.memory_form()
-        launch = {"tile_x": L.launch_shape()[0], "streaming_stores": nts, "nontemporal_loads": ntl}
+        launch = {"tile_x": L.launch_shape()[0], "streaming_stores": nts, "nontemporal_loads": ntl,
+                  "trial_ms": [round(float(v), 4) for v in ms]}
     L.step(warmup)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)

@@ -293,10 +293,10 @@ rlbm_status rlbm_get_memory_form(rlbm_lattice *lat, int *streaming_stores, int *
  * loads and stores, streaming stores, non-temporal loads, both --
  * (two rounds, the second in the reverse order, each candidate timed over
  * trial_steps steps after 2 warm-up steps with HIP events on the lattice's
- * stream and keeping the faster of its two runs), keep the fastest, and
- * remember it for
- * lattices of the same device architecture, storage, size and mask use in
- * this process (and in the text file named by the environment variable
+ * stream and keeping the faster of its two runs), keep the fastest (the
+ * setting on entry stays unless the fastest beats it by more than 1%), and
+ * remember it for lattices of the same device architecture, storage, size
+ * and mask use in this process (and in the text file named by the environment variable
  * RLBM_TUNE_CACHE, if set, which later processes read at rlbm_create).  The
  * lattice state, time and fields are restored afterwards.  ms_per_step
  * (optional, 12 entries since ABI version 2, caller-owned) receives those

@@ -1022,6 +1022,16 @@ rlbm_status rlbm_autotune(rlbm_lattice *L, int trial_steps, double *ms_per_step)
             best_form = c / 3;
         }
     }
+    // the setting on entry stays unless the fastest candidate beats it by
+    // more than 1%: closer than that, short trials do not rank two settings
+    // reliably (they run at other clocks than a long run does)
+    for (int tc = 0; tc < 3; ++tc) {
+        const int c0 = form0 * 3 + tc;
+        if (tiles[tc] == shape0.tile_x && std::isfinite(per_c[c0]) && best >= 0.99 * per_c[c0]) {
+            best_tile = shape0.tile_x;
+            best_form = form0;
+        }
+    }
     // restore
     L->cur = cur0;
     if (e == hipSuccess) e = hipMemcpyAsync(L->pop[cur0], sv, pb, hipMemcpyDeviceToDevice, L->stream);
