@@ -277,9 +277,9 @@ rlbm_status rlbm_set_streaming_stores(rlbm_lattice *lat, int on);
  * kernel whose interior loads do not allocate in the caches, which leaves
  * the Infinity Cache to the populations the step stores (the next step's
  * input).  Pays off where one population array fits the 256 MB cache but
- * the two do not (FP64 at 1024 x 512: 9% faster with ordinary stores);
- * elsewhere it is slower (3-14% on the graphene sample).  Off by default; the
- * autotuner decides.  Results are identical either way.  Batches always use
+ * the two do not (FP64 at 1024 x 512: 4-5% faster than the best form
+ * with ordinary loads); elsewhere it is slower (3-12% on the graphene
+ * sample).  Off by default; the autotuner decides.  Results are identical either way.  Batches always use
  * ordinary loads.  Any nonzero on counts as 1. */
 rlbm_status rlbm_set_streaming_loads(rlbm_lattice *lat, int on);
 
