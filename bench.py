@@ -93,9 +93,10 @@ def run_gpu(w, storage, steps, warmup, autotune=True):
     L = make_lattice(w, storage, stream.cuda_stream)
     launch = None
     if autotune:
-        # about 300 M site updates per candidate run (35 steps at 4096 x 2048,
-        # 572 at 1024 x 512), so that small lattices are not timed on noise
-        ms = L.autotune(max(10, 300_000_000 // (w["nx"] * w["ny"])))
+        # about 250 GB of algorithmic traffic per candidate run (45 ms at
+        # 5.5 TB/s: 78 steps of FP32 at 4096 x 2048, 621 of FP64 at 1024 x 512),
+        # so that every candidate is timed at the clocks a long run settles at
+        ms = L.autotune(max(10, 250_000_000_000 // (2 * 48 * BYTES_PER_POP[storage] * w["nx"] * w["ny"])))
         nts, ntl = L.memory_form()
         launch = {"tile_x": L.launch_shape()[0], "streaming_stores": nts, "nontemporal_loads": ntl,
                   "trial_ms": [round(float(v), 4) for v in ms]}
