@@ -618,6 +618,7 @@ def main(argv=None):
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(secs * 1e3 / args.steps, 5),
+        "timed_seconds": round(secs, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
