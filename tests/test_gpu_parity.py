@@ -384,20 +384,26 @@ def test_bandwidth_probe_runs_every_pattern():
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16dev"])
-def test_memory_forms_agree(storage):
+@pytest.mark.parametrize("variant", ["drive", "lca", "no_table"])
+def test_memory_forms_agree(storage, variant):
     """Streaming stores and non-temporal loads, alone or together, give
-    bit-identical populations (they change only how the caches are used)."""
+    bit-identical populations (they change only how the caches are used),
+    in every force mode and gather mode of the step kernel."""
     w = workloads.small_device(nx=300, ny=33, steps=5)
-    ref = gpu_lattice(w, storage)
+    if variant == "lca":
+        w["cg"] = 2.0
+    table = variant != "no_table"
+    ref = gpu_lattice(w, storage, table=table)
     ref.set_streaming_stores(False)
     ref.set_streaming_loads(False)
     ref.step(5)
     a = ref.read_populations()
     for nt_store, nt_load in ((True, False), (False, True), (True, True)):
-        _say(f"memory form {storage} stores={nt_store} loads={nt_load}")
-        G = gpu_lattice(w, storage)
+        _say(f"memory form {storage} {variant} stores={nt_store} loads={nt_load}")
+        G = gpu_lattice(w, storage, table=table)
         G.set_streaming_stores(nt_store)
         G.set_streaming_loads(nt_load)
+        assert G.memory_form() == (nt_store, nt_load)
         G.step(5)
         assert np.array_equal(a, G.read_populations()), (nt_store, nt_load)
         G.close()
